@@ -1,0 +1,196 @@
+/*
+ * ocd.h -- C ABI of libocd.so: optimized coordinate descent (OCD) soft-output
+ * data detection for massive MU-MIMO-OFDM on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: M. Wu, C. Dick, J. R. Cavallaro, C. Studer, "High-Throughput Data
+ * Detection for Massive MU-MIMO-OFDM using Coordinate Descent", arXiv 1611.08779.
+ *
+ * What is computed.  For every subcarrier w and every OFDM symbol s sharing
+ * the channel matrix H_w, the receive vector y_{w,s} (B antennas) is equalised
+ * by Algorithm 1 (OCD, Section III-B) in MMSE mode (regulariser N0/Es, no
+ * constraint), BOX mode (no regulariser, every real and imaginary part clipped
+ * to [-beta, beta], equation eq:projection) or HYBRID mode (both, with one
+ * regulariser per sweep).  The K sweeps visit users u = 1..U in order and keep
+ * the residual r = y - H z up to date incrementally (equation eq:residual).
+ * The soft output is the max-log LLR of equation eq:exactinversellr with
+ * Section III-C's approximations mu = d_u^-1 ||h_u||^2 and
+ * rho = mu / (1 - mu) (= ||h_u||^2 / lambda_K).  In BOX mode, where that
+ * formula gives mu = 1 and an infinite rho, rho = ||h_u||^2 Es / N0 is used.
+ * LLR sign: L > 0 favours bit 1.  Constellation: Gray square QAM with Q in
+ * {2, 4, 6} bits, unit average energy times Es; per axis the level index m
+ * (increasing amplitude) carries the label m ^ (m >> 1), Q/2 bits MSB first,
+ * in-phase bits before quadrature bits.
+ *
+ * Memory.  Every array argument is a DEVICE pointer, allocated, owned and
+ * freed by the caller; the library never keeps a pointer after the call
+ * returns (except inside a graph built by ocd_detect_jobs, see there), and
+ * never allocates device memory itself.  Complex arrays hold interleaved
+ * (re, im) pairs: float2 for OCD_STORE_F32, IEEE half pairs for OCD_STORE_F16
+ * (inputs H and y only; every output is FP32).  Layouts, C order:
+ *   H      [W][U][B]      column h_u of subcarrier w contiguous
+ *   y      [W][S][B]
+ *   z      [W][S][U]      complex FP32, the equalised estimate z^(K)
+ *   z_hist [W][S][K][U]   complex FP32, z^(k) after every sweep k = 1..K
+ *   llr    [W][S][U][Q]   FP32
+ *   g      [W][U]         FP32, ||h_u||^2
+ *   dinv,p [W][Kt][U]     FP32, Kt = K if lambda != NULL else 1
+ *   dy     [W][S][B]      complex FP32
+ *
+ * Execution.  Work is enqueued asynchronously on `stream` (NULL = the default
+ * stream of the current device); nothing synchronises the host except where
+ * stated.  Calls that overlap on one stream are ordered by the stream.
+ *
+ * Errors.  Every entry point returns an ocd_status.  Arguments are validated
+ * before any device work is enqueued; on OCD_EINVAL or OCD_EUNSUPPORTED
+ * nothing was launched and no output was touched.  OCD_EDEVICE reports a HIP
+ * runtime error from a launch (outputs are then unspecified).  Nothing throws,
+ * aborts or prints across the ABI.
+ */
+#ifndef OCD_H
+#define OCD_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OCD_OK = 0,
+    OCD_EINVAL = -1,       /* bad shape, scalar or pointer */
+    OCD_EUNSUPPORTED = -2, /* valid problem this build does not handle (e.g. LDS too small) */
+    OCD_EDEVICE = -3       /* HIP runtime error */
+} ocd_status;
+
+typedef enum { OCD_MMSE = 0, OCD_BOX = 1, OCD_HYBRID = 2 } ocd_mode;
+typedef enum { OCD_STORE_F32 = 0, OCD_STORE_F16 = 1 } ocd_storage;
+
+/* The problem statement (Section II-A and Algorithm 1's inputs).
+ *   B        BS antennas (rows of H_w), 1 <= B <= 1024
+ *   U        users (columns of H_w), 1 <= U <= min(B, 32)   (run-time limit U <= 32, Section V-A)
+ *   W        subcarriers, >= 0
+ *   S        OFDM symbols sharing H_w, >= 1
+ *   Q        bits per QAM symbol: 2, 4 or 6
+ *   K        OCD sweeps, 1 <= K <= 256                       (run-time limit K <= 256, Section V-A)
+ *   mode     ocd_mode
+ *   storage  ocd_storage of H and y
+ *   N0       noise variance per complex receive entry, > 0 (sets the MMSE regulariser
+ *            N0/Es and the BOX-mode SINR)
+ *   Es       average symbol energy, > 0
+ *   beta     box half-width for BOX/HYBRID; <= 0 selects the constellation edge
+ *            max Re{a} * sqrt(Es) (Section II-D). Ignored in MMSE mode. */
+typedef struct {
+    int B, U, W, S, Q, K;
+    int mode;
+    int storage;
+    float N0, Es, beta;
+} ocd_problem;
+
+/* Human-readable name of a status code (static string). */
+const char *ocd_status_str(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int ocd_version(void);
+
+/* Algorithm 1 preprocessing: g_u = ||h_u||^2, d_u^-1 = (g_u + lambda_k)^-1 and
+ * p_u = d_u^-1 g_u for every subcarrier.
+ *   lambda  device [K] per-sweep regulariser, or NULL for the mode's default
+ *           (N0/Es in MMSE and HYBRID, 0 in BOX); entries must be >= 0.
+ *   g       device [W][U], dinv and p device [W][Kt][U] (Kt = K if lambda else 1).
+ * A column with g_u + lambda_k = 0 gets dinv = 0 (that user is never updated). */
+ocd_status ocd_preprocess(const ocd_problem *pb, const void *H, const float *lambda,
+                          float *g, float *dinv, float *p, hipStream_t stream);
+
+/* Algorithm 1 plus the soft output, fused in one launch.
+ *   g, dinv, p  either all NULL (preprocessing fused into the kernel) or all outputs
+ *               of ocd_preprocess for the same H and lambda.
+ *   z, llr, z_hist  outputs, each may be NULL (not written); z_hist is what
+ *               ocd_detect_backward needs.
+ * Uses the launch plan cached for this shape (see ocd_autotune), else a heuristic. */
+ocd_status ocd_detect(const ocd_problem *pb, const void *H, const void *y, const float *lambda,
+                      const float *g, const float *dinv, const float *p,
+                      float *z, float *llr, float *z_hist, hipStream_t stream);
+
+/* Bytes of device workspace ocd_detect_backward needs for this problem. */
+size_t ocd_backward_workspace_bytes(const ocd_problem *pb);
+
+/* Adjoint of ocd_detect with respect to the per-sweep regularisers, the box
+ * half-width and the receive vectors (H is not differentiated).  The K sweeps
+ * are reversed one coordinate update at a time; the residual before every
+ * update is recovered from the one after it (r_pre = r_post + h_u Delta) rather
+ * than stored, so only z_hist is kept from the forward pass.
+ *   z_hist      device [W][S][K][U], written by ocd_detect with the same arguments
+ *   dllr        device [W][S][U][Q], dLoss/dLLR
+ *   dlambda     device [K]  dLoss/dlambda_k (overwritten)
+ *   dbeta       device [1]  dLoss/dbeta (overwritten; 0 in MMSE mode)
+ *   dy          device [W][S][B] complex FP32, dLoss/dRe y + j dLoss/dIm y (may be NULL)
+ *   workspace   device, >= ocd_backward_workspace_bytes(pb) bytes, 16-byte aligned
+ * dlambda and dbeta are reduced in a fixed order: repeated calls give identical bits.
+ * Subgradient conventions: |c| <= beta counts as unclipped; the max-log minimisers
+ * are the first ones found. */
+ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void *y,
+                               const float *lambda, const float *z_hist, const float *dllr,
+                               float *dlambda, float *dbeta, float *dy,
+                               void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* A launch plan: how vectors map onto lanes and workgroups.
+ *   lanes_per_vector   lanes that share one (subcarrier, symbol) vector: 4, 8, 16 or 32
+ *   vectors_per_block  vectors per workgroup (1..512/lanes_per_vector); H of every
+ *                      subcarrier a workgroup touches is staged once into LDS
+ *   xcd_remap          1: consecutive tiles go to the same XCD (shared L2) */
+typedef struct {
+    int lanes_per_vector;
+    int vectors_per_block;
+    int xcd_remap;
+    int reserved;
+} ocd_plan;
+
+/* The plan ocd_detect would use for this problem (cached or heuristic). */
+ocd_status ocd_get_plan(const ocd_problem *pb, ocd_plan *plan);
+
+/* Force a plan for this problem's shape (B, U, S, K, Q, mode, storage). */
+ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
+
+/* Autotuner: times every valid plan for this problem on the caller's buffers
+ * (outputs are overwritten; z and llr must be non-NULL), caches the fastest
+ * for the shape and returns it.  Synchronises `stream`.  When the environment
+ * variable OCD_TUNE_CACHE names a file, plans are also loaded from and saved
+ * to that JSON file, keyed by GPU architecture and shape. */
+ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,
+                        float *z, float *llr, int repeats, ocd_plan *best, hipStream_t stream);
+
+/* Batched detection of uneven jobs in one persistent launch.
+ * Each job j is a full problem (jobs[j]) with its own device arrays H[j], y[j],
+ * z[j] (may be NULL) and llr[j] (may be NULL); every job must use the default
+ * regulariser (lambda = NULL) and the same storage.  Jobs are cut into tiles,
+ * ordered longest-first, and persistent workgroups pop tiles from a device
+ * queue until it is empty.
+ *   workspace   device, >= ocd_jobs_workspace_bytes(jobs, n_jobs), 256-byte aligned;
+ *               holds the tile table and the queue head.
+ *   flags       OCD_JOBS_GRAPH: capture {queue reset, persistent kernel} in a
+ *               hipGraph on the first call for this workspace and replay it on
+ *               later calls with the same job list (pointers are read from the
+ *               workspace, so only the table is re-uploaded when they change).
+ *               OCD_JOBS_TUNE: before running, time every tile-size policy on the
+ *               caller's buffers (outputs are overwritten; synchronises `stream`)
+ *               and keep the fastest for this list of job shapes.
+ * The call enqueues a host-to-device copy of the tile table from pinned memory
+ * held by the library and waits for the previous upload from the same
+ * workspace, so it may block until earlier work on `stream` has consumed it. */
+#define OCD_JOBS_GRAPH 1
+#define OCD_JOBS_TUNE 2
+size_t ocd_jobs_workspace_bytes(const ocd_problem *jobs, int n_jobs);
+ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const *H, const void *const *y,
+                           float *const *z, float *const *llr, int n_jobs,
+                           void *workspace, size_t workspace_bytes, int flags, hipStream_t stream);
+
+/* Drops every cached hipGraph and pinned staging buffer (e.g. before freeing a
+ * workspace that ocd_detect_jobs captured). */
+void ocd_release_graphs(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCD_H */

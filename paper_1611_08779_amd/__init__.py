@@ -1,0 +1,351 @@
+"""Python binding of libocd.so: OCD soft-output MU-MIMO-OFDM detection on MI355X.
+
+The functions named ``ocd_*`` mirror the C ABI declared in ``include/ocd.h``
+one to one; they only marshal torch device tensors into pointers, check that
+every buffer is large enough for the problem, and pass torch's current HIP
+stream.  All arithmetic runs in the HIP kernels of ``libocd.so``; there is no
+other implementation and no fallback: if the library is not built, importing
+this package raises.
+
+Convenience wrappers (:func:`detect`, :func:`preprocess`, :func:`backward`,
+:func:`detect_jobs`) allocate outputs with torch and return them.
+
+Tensor conventions (device tensors, C-contiguous):
+
+* FP32 storage: ``H`` complex64 ``[W, U, B]``, ``y`` complex64 ``[W, S, B]``
+  (float32 with a trailing dimension of 2 is accepted too).
+* FP16 storage: ``H`` float16 ``[W, U, B, 2]``, ``y`` float16 ``[W, S, B, 2]``.
+* ``z`` complex64 ``[W, S, U]``, ``llr`` float32 ``[W, S, U, Q]``,
+  ``z_hist`` complex64 ``[W, S, K, U]``, ``lam`` float32 ``[K]``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "Problem", "Plan", "OCDError", "MODES", "STORAGES", "LIB_PATH",
+    "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
+    "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_get_plan", "ocd_set_plan",
+    "ocd_autotune", "ocd_jobs_workspace_bytes", "ocd_detect_jobs", "ocd_release_graphs",
+    "problem", "detect", "preprocess", "backward", "detect_jobs", "OCD_JOBS_GRAPH", "OCD_JOBS_TUNE",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libocd.so")
+
+MODES = {"mmse": 0, "box": 1, "hybrid": 2}
+STORAGES = {"f32": 0, "f16": 1}
+OCD_JOBS_GRAPH = 1
+OCD_JOBS_TUNE = 2
+
+_STATUS = {0: "OCD_OK", -1: "OCD_EINVAL", -2: "OCD_EUNSUPPORTED", -3: "OCD_EDEVICE"}
+
+
+class Problem(ctypes.Structure):
+    """``ocd_problem``: B, U, W, S, Q, K, mode, storage, N0, Es, beta."""
+
+    _fields_ = [("B", ctypes.c_int), ("U", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int),
+                ("Q", ctypes.c_int), ("K", ctypes.c_int), ("mode", ctypes.c_int),
+                ("storage", ctypes.c_int), ("N0", ctypes.c_float), ("Es", ctypes.c_float),
+                ("beta", ctypes.c_float)]
+
+    def __repr__(self):
+        return ("Problem(B=%d, U=%d, W=%d, S=%d, Q=%d, K=%d, mode=%d, storage=%d, N0=%g, Es=%g, "
+                "beta=%g)" % (self.B, self.U, self.W, self.S, self.Q, self.K, self.mode,
+                              self.storage, self.N0, self.Es, self.beta))
+
+
+class Plan(ctypes.Structure):
+    """``ocd_plan``: lanes per vector, vectors per workgroup, XCD remap."""
+
+    _fields_ = [("lanes_per_vector", ctypes.c_int), ("vectors_per_block", ctypes.c_int),
+                ("xcd_remap", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"lanes_per_vector": self.lanes_per_vector,
+                "vectors_per_block": self.vectors_per_block, "xcd_remap": self.xcd_remap}
+
+
+class OCDError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__("%s failed: %s" % (fn, _STATUS.get(status, status)))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libocd.so is not built: run `python -m paper_1611_08779_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(Problem)
+    vp, fp, sz = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t
+    sigs = {
+        "ocd_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "ocd_version": ([], ctypes.c_int),
+        "ocd_preprocess": ([P, vp, fp, fp, fp, fp, vp], ctypes.c_int),
+        "ocd_detect": ([P, vp, vp, fp, fp, fp, fp, fp, fp, fp, vp], ctypes.c_int),
+        "ocd_backward_workspace_bytes": ([P], sz),
+        "ocd_detect_backward": ([P, vp, vp, fp, fp, fp, fp, fp, fp, vp, sz, vp], ctypes.c_int),
+        "ocd_get_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
+        "ocd_set_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
+        "ocd_autotune": ([P, vp, vp, fp, fp, ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
+        "ocd_jobs_workspace_bytes": ([P, ctypes.c_int], sz),
+        "ocd_detect_jobs": ([P, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                             ctypes.POINTER(vp), ctypes.c_int, vp, sz, ctypes.c_int, vp], ctypes.c_int),
+        "ocd_release_graphs": ([], None),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+# ---------------------------------------------------------------- marshalling
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t, name, dtypes, nbytes_min, device=None):
+    """Pointer of a contiguous device tensor of an allowed dtype holding >= nbytes_min."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor (got %s)" % (name, t.device))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+    if t.dtype not in dtypes:
+        raise TypeError("%s has dtype %s, expected one of %s" % (name, t.dtype, dtypes))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    nbytes = t.numel() * t.element_size()
+    if nbytes < nbytes_min:
+        raise ValueError("%s holds %d bytes, the problem needs %d" % (name, nbytes, nbytes_min))
+    return t.data_ptr()
+
+
+def _check(fn, status):
+    if status != 0:
+        raise OCDError(fn, status)
+
+
+def _in_dtypes(pb):
+    return (torch.float16,) if pb.storage == 1 else (torch.complex64, torch.float32)
+
+
+def _cbytes(pb):
+    return 4 if pb.storage == 1 else 8
+
+
+def problem(B, U, W, S, Q, K, mode="mmse", storage="f32", N0=1.0, Es=1.0, beta=0.0) -> Problem:
+    return Problem(int(B), int(U), int(W), int(S), int(Q), int(K),
+                   MODES[mode] if isinstance(mode, str) else int(mode),
+                   STORAGES[storage] if isinstance(storage, str) else int(storage),
+                   float(N0), float(Es), float(beta))
+
+
+# ---------------------------------------------------------------- C ABI, one to one
+
+def ocd_status_str(status: int) -> str:
+    return _lib.ocd_status_str(int(status)).decode()
+
+
+def ocd_version() -> int:
+    return _lib.ocd_version()
+
+
+def ocd_preprocess(pb: Problem, H, lam, g, dinv, p, stream=None) -> None:
+    Kt = pb.K if lam is not None else 1
+    dev = H.device
+    f32 = (torch.float32,)
+    st = _lib.ocd_preprocess(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(g, "g", f32, pb.W * pb.U * 4, dev),
+        _dev_ptr(dinv, "dinv", f32, pb.W * Kt * pb.U * 4, dev),
+        _dev_ptr(p, "p", f32, pb.W * Kt * pb.U * 4, dev), _stream(stream))
+    _check("ocd_preprocess", st)
+
+
+def ocd_detect(pb: Problem, H, y, lam=None, g=None, dinv=None, p=None, z=None, llr=None,
+               z_hist=None, stream=None) -> None:
+    Kt = pb.K if lam is not None else 1
+    dev = H.device
+    f32 = (torch.float32,)
+    zt = (torch.complex64, torch.float32)
+    st = _lib.ocd_detect(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(g, "g", f32, pb.W * pb.U * 4, dev),
+        _dev_ptr(dinv, "dinv", f32, pb.W * Kt * pb.U * 4, dev),
+        _dev_ptr(p, "p", f32, pb.W * Kt * pb.U * 4, dev),
+        _dev_ptr(z, "z", zt, pb.W * pb.S * pb.U * 8, dev),
+        _dev_ptr(llr, "llr", f32, pb.W * pb.S * pb.U * pb.Q * 4, dev),
+        _dev_ptr(z_hist, "z_hist", zt, pb.W * pb.S * pb.K * pb.U * 8, dev), _stream(stream))
+    _check("ocd_detect", st)
+
+
+def ocd_backward_workspace_bytes(pb: Problem) -> int:
+    return int(_lib.ocd_backward_workspace_bytes(ctypes.byref(pb)))
+
+
+def ocd_detect_backward(pb: Problem, H, y, lam, z_hist, dllr, dlam, dbeta, dy, workspace,
+                        stream=None) -> None:
+    dev = H.device
+    f32 = (torch.float32,)
+    zt = (torch.complex64, torch.float32)
+    ws_need = ocd_backward_workspace_bytes(pb)
+    st = _lib.ocd_detect_backward(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(z_hist, "z_hist", zt, pb.W * pb.S * pb.K * pb.U * 8, dev),
+        _dev_ptr(dllr, "dllr", f32, pb.W * pb.S * pb.U * pb.Q * 4, dev),
+        _dev_ptr(dlam, "dlam", f32, pb.K * 4, dev),
+        _dev_ptr(dbeta, "dbeta", f32, 4, dev),
+        _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
+        _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, _stream(stream))
+    _check("ocd_detect_backward", st)
+
+
+def ocd_get_plan(pb: Problem) -> Plan:
+    pl = Plan()
+    _check("ocd_get_plan", _lib.ocd_get_plan(ctypes.byref(pb), ctypes.byref(pl)))
+    return pl
+
+
+def ocd_set_plan(pb: Problem, plan: Plan) -> None:
+    _check("ocd_set_plan", _lib.ocd_set_plan(ctypes.byref(pb), ctypes.byref(plan)))
+
+
+def ocd_autotune(pb: Problem, H, y, z, llr, repeats=5, stream=None) -> Plan:
+    dev = H.device
+    pl = Plan()
+    st = _lib.ocd_autotune(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(z, "z", (torch.complex64, torch.float32), pb.W * pb.S * pb.U * 8, dev),
+        _dev_ptr(llr, "llr", (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev),
+        int(repeats), ctypes.byref(pl), _stream(stream))
+    _check("ocd_autotune", st)
+    return pl
+
+
+def _problem_array(jobs):
+    arr = (Problem * len(jobs))()
+    for i, pb in enumerate(jobs):
+        arr[i] = pb
+    return arr
+
+
+def ocd_jobs_workspace_bytes(jobs) -> int:
+    arr = _problem_array(jobs)
+    return int(_lib.ocd_jobs_workspace_bytes(arr, len(jobs)))
+
+
+def ocd_detect_jobs(jobs, H, y, z, llr, workspace, flags=0, stream=None) -> None:
+    n = len(jobs)
+    arr = _problem_array(jobs)
+    ptrs = [(ctypes.c_void_p * n)() for _ in range(4)]
+    dev = H[0].device
+    for j, pb in enumerate(jobs):
+        ptrs[0][j] = _dev_ptr(H[j], "H[%d]" % j, _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb), dev)
+        ptrs[1][j] = _dev_ptr(y[j], "y[%d]" % j, _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev)
+        ptrs[2][j] = _dev_ptr(z[j] if z is not None else None, "z[%d]" % j,
+                              (torch.complex64, torch.float32), pb.W * pb.S * pb.U * 8, dev)
+        ptrs[3][j] = _dev_ptr(llr[j] if llr is not None else None, "llr[%d]" % j,
+                              (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev)
+    ws_need = ocd_jobs_workspace_bytes(jobs)
+    if ws_need == 0:
+        raise OCDError("ocd_jobs_workspace_bytes", -1)
+    wsp = _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev)
+    if wsp % 256:
+        raise ValueError("workspace must be 256-byte aligned")
+    st = _lib.ocd_detect_jobs(arr, ptrs[0], ptrs[1], ptrs[2] if z is not None else None,
+                              ptrs[3] if llr is not None else None, n, wsp, ws_need, int(flags),
+                              _stream(stream))
+    _check("ocd_detect_jobs", st)
+
+
+def ocd_release_graphs() -> None:
+    _lib.ocd_release_graphs()
+
+
+# ---------------------------------------------------------------- convenience
+
+def _shape_of(H, y, storage):
+    if storage == "f16" or (isinstance(storage, int) and storage == 1):
+        W, U, B = H.shape[:3]
+        S = y.shape[1]
+    elif H.dtype == torch.complex64:
+        W, U, B = H.shape
+        S = y.shape[1]
+    else:
+        W, U, B = H.shape[:3]
+        S = y.shape[1]
+    return W, U, B, S
+
+
+def preprocess(H, K, Q, mode="mmse", N0=1.0, Es=1.0, lam=None, storage="f32", stream=None):
+    """Returns (g [W,U], dinv [W,Kt,U], p [W,Kt,U])."""
+    W, U, B = H.shape[:3]
+    pb = problem(B, U, W, 1, Q, K, mode, storage, N0, Es)
+    Kt = K if lam is not None else 1
+    g = torch.empty(W, U, device=H.device, dtype=torch.float32)
+    dinv = torch.empty(W, Kt, U, device=H.device, dtype=torch.float32)
+    p = torch.empty(W, Kt, U, device=H.device, dtype=torch.float32)
+    ocd_preprocess(pb, H, lam, g, dinv, p, stream)
+    return g, dinv, p
+
+
+def detect(H, y, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, lam=None, storage="f32",
+           want_z=True, want_llr=True, want_hist=False, pre=None, stream=None):
+    """Runs ocd_detect; returns (z, llr, z_hist) with None for outputs not asked for."""
+    W, U, B, S = _shape_of(H, y, storage)
+    pb = problem(B, U, W, S, Q, K, mode, storage, N0, Es, beta)
+    dev = H.device
+    z = torch.empty(W, S, U, device=dev, dtype=torch.complex64) if want_z else None
+    llr = torch.empty(W, S, U, Q, device=dev, dtype=torch.float32) if want_llr else None
+    zh = torch.empty(W, S, K, U, device=dev, dtype=torch.complex64) if want_hist else None
+    g, dinv, p = pre if pre is not None else (None, None, None)
+    ocd_detect(pb, H, y, lam, g, dinv, p, z, llr, zh, stream)
+    return z, llr, zh
+
+
+def backward(H, y, z_hist, dllr, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, lam=None,
+             storage="f32", want_dy=True, stream=None):
+    """Runs ocd_detect_backward; returns (dlam [K], dbeta [1], dy [W,S,B] or None)."""
+    W, U, B, S = _shape_of(H, y, storage)
+    pb = problem(B, U, W, S, Q, K, mode, storage, N0, Es, beta)
+    dev = H.device
+    dlam = torch.empty(K, device=dev, dtype=torch.float32)
+    dbeta = torch.empty(1, device=dev, dtype=torch.float32)
+    dy = torch.empty(W, S, B, device=dev, dtype=torch.complex64) if want_dy else None
+    ws = torch.empty(ocd_backward_workspace_bytes(pb), device=dev, dtype=torch.uint8)
+    ocd_detect_backward(pb, H, y, lam, z_hist, dllr, dlam, dbeta, dy, ws, stream)
+    return dlam, dbeta, dy
+
+
+def detect_jobs(jobs, H, y, flags=0, workspace=None, stream=None):
+    """Runs ocd_detect_jobs on a list of Problems; returns (z list, llr list, workspace)."""
+    dev = H[0].device
+    z = [torch.empty(pb.W, pb.S, pb.U, device=dev, dtype=torch.complex64) for pb in jobs]
+    llr = [torch.empty(pb.W, pb.S, pb.U, pb.Q, device=dev, dtype=torch.float32) for pb in jobs]
+    if workspace is None:
+        workspace = torch.empty(ocd_jobs_workspace_bytes(jobs) + 256, device=dev, dtype=torch.uint8)
+    ocd_detect_jobs(jobs, H, y, z, llr, workspace, flags, stream)
+    return z, llr, workspace

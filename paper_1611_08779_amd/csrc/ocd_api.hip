@@ -1,0 +1,457 @@
+// ocd_api.hip -- the C ABI of libocd.so: argument validation, launch plans
+// (heuristic, cache, autotuner) and the launches of the forward, preprocessing
+// and adjoint kernels.  Batched jobs live in ocd_jobs.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ocd.h"
+#include "ocd_api_internal.h"
+#include "ocd_device.h"
+#include "ocd_internal.h"
+
+using namespace ocd;
+
+// ------------------------------------------------------------------ status
+
+extern "C" const char *ocd_status_str(int status)
+{
+    switch (status) {
+    case OCD_OK: return "OCD_OK";
+    case OCD_EINVAL: return "OCD_EINVAL: invalid argument";
+    case OCD_EUNSUPPORTED: return "OCD_EUNSUPPORTED: problem not supported by this build";
+    case OCD_EDEVICE: return "OCD_EDEVICE: HIP runtime error";
+    default: return "unknown ocd_status";
+    }
+}
+
+extern "C" int ocd_version(void) { return 10000; }
+
+// ------------------------------------------------------------------ validation
+
+namespace ocd {
+
+static bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+ocd_status validate(const ocd_problem *pb)
+{
+    if (!pb) return OCD_EINVAL;
+    if (pb->B < 1 || pb->B > 1024) return OCD_EINVAL;
+    if (pb->U < 1 || pb->U > 32 || pb->U > pb->B) return OCD_EINVAL;
+    if (pb->W < 0 || pb->S < 1) return OCD_EINVAL;
+    if (pb->Q != 2 && pb->Q != 4 && pb->Q != 6) return OCD_EINVAL;
+    if (pb->K < 1 || pb->K > 256) return OCD_EINVAL;
+    if (pb->mode != OCD_MMSE && pb->mode != OCD_BOX && pb->mode != OCD_HYBRID) return OCD_EINVAL;
+    if (pb->storage != OCD_STORE_F32 && pb->storage != OCD_STORE_F16) return OCD_EINVAL;
+    if (!finite_pos(pb->N0) || !finite_pos(pb->Es) || !std::isfinite(pb->beta)) return OCD_EINVAL;
+    if ((long long)pb->W * pb->S > (1LL << 30)) return OCD_EUNSUPPORTED;
+    return OCD_OK;
+}
+
+int lds_limit_bytes()
+{
+    static int limit = -1;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (limit < 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            limit = (int)prop.sharedMemPerBlock;
+        else
+            limit = 65536;
+    }
+    return limit;
+}
+
+// gfx architecture of the current device (queried once per device).
+std::string arch_name()
+{
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string a = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        a = prop.gcnArchName;
+        size_t c = a.find(':');
+        if (c != std::string::npos) a = a.substr(0, c);
+    }
+    names[dev] = a;
+    return a;
+}
+
+float box_edge(int Q)
+{
+    const int M = 1 << (Q / 2);
+    return (float)(M - 1) * qam_scale(Q);
+}
+
+// Complex entries per lane for a group of L lanes: the smallest power of two
+// >= B / L, at least 2; 0 if above 32.
+int npl_for(int B, int L)
+{
+    int n = 2;
+    while (n * L < B) n *= 2;
+    return n <= 32 ? n : 0;
+}
+
+// Fills the launch parameters of a (problem, plan) pair; false if the plan is
+// not valid for the problem (group too small for B, LDS too small, ...).
+bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda, bool backward,
+                 Params &P, int &npl, int &threads, size_t &lds)
+{
+    const int L = pl.lanes_per_vector;
+    if (L != 4 && L != 8 && L != 16 && L != 32) return false;
+    npl = npl_for(pb->B, L);
+    if (!npl) return false;
+    const int cap = 512 / L;
+    if (pl.vectors_per_block < 1 || pl.vectors_per_block > cap) return false;
+    std::memset(&P, 0, sizeof(P));
+    P.B = pb->B; P.U = pb->U; P.W = pb->W; P.S = pb->S; P.K = pb->K; P.Q = pb->Q;
+    P.box = pb->mode != OCD_MMSE;
+    P.per_sweep = lambda != nullptr;
+    P.Bpad = L * npl;
+    P.vpb = pl.vectors_per_block;
+    if (P.vpb % P.S == 0) P.maxslots = P.vpb / P.S;
+    else P.maxslots = std::min(P.vpb, (P.vpb - 1) / P.S + 2);
+    const int row = P.U * P.Bpad;             // float2 per slot, before padding
+    P.slot_stride = row + ((row % 16 == 0) ? 8 : (16 - row % 16 + 8) % 16);
+    P.xcd_remap = pl.xcd_remap ? 1 : 0;
+    P.Es = pb->Es; P.N0 = pb->N0;
+    P.beta = pb->beta > 0.f ? pb->beta : box_edge(pb->Q) * std::sqrt(pb->Es);
+    P.lam_default = pb->mode == OCD_BOX ? 0.f : pb->N0 / pb->Es;
+    P.lambda = lambda;
+    const long nvec = (long)pb->W * pb->S;
+    P.nblocks = (int)((nvec + P.vpb - 1) / P.vpb);
+    const int waves = (P.vpb * L + 63) / 64;
+    threads = waves * 64;
+    lds = lds_bytes(P, threads / L, backward);
+    return lds <= (size_t)lds_limit_bytes();
+}
+
+// Rough occupancy model used by the heuristic: lanes doing useful work per CU.
+static double plan_score(const ocd_problem *pb, const ocd_plan &pl, const Params &P, int npl,
+                         int threads, size_t lds)
+{
+    const int lds_cu = 160 * 1024;
+    const int vgpr = 4 * npl + 40;
+    const int waves_simd = std::max(1, std::min(8, 512 / vgpr));
+    const int blocks_lds = (int)std::max<size_t>(1, lds_cu / std::max<size_t>(lds, 1));
+    const int blocks_thr = std::max(1, (4 * waves_simd * 64) / threads);
+    const int blocks = std::min(blocks_lds, blocks_thr);
+    double useful = (double)P.vpb * pl.lanes_per_vector / threads;     // idle groups
+    double eff = (double)pb->B / P.Bpad;                               // zero padding
+    return blocks * threads * useful * eff;
+}
+
+ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backward)
+{
+    int L = 4;
+    while (L < 32 && L * 16 < pb->B) L *= 2;
+    ocd_plan best = {L, 1, 0, 0};
+    double best_score = -1;
+    const int cap = 512 / L;
+    std::vector<int> cands;
+    for (int v = cap; v >= 1; v /= 2) cands.push_back(v);
+    for (int m = pb->S; m <= cap; m += pb->S) cands.push_back(m);
+    for (int v : cands) {
+        ocd_plan pl = {L, v, 0, 0};
+        Params P;
+        int npl, threads;
+        size_t lds;
+        if (!make_params(pb, pl, lambda, backward, P, npl, threads, lds)) continue;
+        double s = plan_score(pb, pl, P, npl, threads, lds);
+        if (s > best_score * 1.02 || (s > best_score * 0.98 && v > best.vectors_per_block)) {
+            best_score = std::max(s, best_score);
+            best = pl;
+        }
+    }
+    return best;
+}
+
+// ------------------------------------------------------------------ plan cache
+
+static std::mutex g_plan_mu;
+static std::map<std::string, ocd_plan> g_plans;
+static bool g_plans_loaded = false;
+
+std::string plan_key(const ocd_problem *pb, bool per_sweep, bool backward)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|%s|B%d|U%d|W%d|S%d|K%d|Q%d|m%d|s%d|l%d", arch_name().c_str(),
+                  backward ? "bwd" : "fwd", pb->B, pb->U, pb->W, pb->S, pb->K, pb->Q, pb->mode,
+                  pb->storage, per_sweep ? 1 : 0);
+    return buf;
+}
+
+static void load_plan_file_locked()
+{
+    if (g_plans_loaded) return;
+    g_plans_loaded = true;
+    const char *path = std::getenv("OCD_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char key[256];
+        ocd_plan pl = {0, 0, 0, 0};
+        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"lanes_per_vector\": %d, "
+                              "\"vectors_per_block\": %d, \"xcd_remap\": %d",
+                        key, &pl.lanes_per_vector, &pl.vectors_per_block, &pl.xcd_remap) == 4)
+            g_plans[key] = pl;
+    }
+    std::fclose(f);
+}
+
+static void save_plan_file_locked()
+{
+    const char *path = std::getenv("OCD_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto &kv : g_plans)
+        std::fprintf(f, "{\"key\": \"%s\", \"lanes_per_vector\": %d, \"vectors_per_block\": %d, "
+                        "\"xcd_remap\": %d}\n",
+                     kv.first.c_str(), kv.second.lanes_per_vector, kv.second.vectors_per_block,
+                     kv.second.xcd_remap);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+bool cached_plan(const std::string &key, ocd_plan &pl)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    load_plan_file_locked();
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) return false;
+    pl = it->second;
+    return true;
+}
+
+void store_plan(const std::string &key, const ocd_plan &pl, bool persist)
+{
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    load_plan_file_locked();
+    g_plans[key] = pl;
+    if (persist) save_plan_file_locked();
+}
+
+ocd_plan choose_plan(const ocd_problem *pb, const float *lambda, bool backward)
+{
+    ocd_plan pl;
+    if (cached_plan(plan_key(pb, lambda != nullptr, backward), pl)) {
+        Params P;
+        int npl, threads;
+        size_t lds;
+        if (make_params(pb, pl, lambda, backward, P, npl, threads, lds)) return pl;
+    }
+    return heuristic_plan(pb, lambda, backward);
+}
+
+static bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+void set_vec_ok(Params &P, const ocd_problem *pb, const void *H, const void *y)
+{
+    const size_t a = pb->storage == OCD_STORE_F16 ? 8 : 16;
+    P.vec_ok = (pb->B % 2 == 0) && aligned(H, a) && (y == nullptr || aligned(y, a));
+}
+
+}  // namespace ocd
+
+// ------------------------------------------------------------------ preprocessing
+
+extern "C" ocd_status ocd_preprocess(const ocd_problem *pb, const void *H, const float *lambda,
+                                     float *g, float *dinv, float *p, hipStream_t stream)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (pb->W == 0) return OCD_OK;
+    if (!H || !g || !dinv || !p) return OCD_EINVAL;
+    Params P;
+    std::memset(&P, 0, sizeof P);
+    P.B = pb->B; P.U = pb->U; P.W = pb->W; P.S = pb->S; P.K = pb->K; P.Q = pb->Q;
+    P.per_sweep = lambda != nullptr;
+    P.lam_default = pb->mode == OCD_BOX ? 0.f : pb->N0 / pb->Es;
+    P.lambda = lambda;
+    P.H = H;
+    set_vec_ok(P, pb, H, nullptr);
+    hipError_t e = launch_preprocess(pb->storage == OCD_STORE_F16, P, g, dinv, p, stream);
+    return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}
+
+// ------------------------------------------------------------------ forward
+
+namespace ocd {
+
+ocd_status run_forward(const ocd_problem *pb, const ocd_plan &pl, const void *H, const void *y,
+                       const float *lambda, const float *g, const float *dinv, const float *p,
+                       float *z, float *llr, float *z_hist, hipStream_t stream)
+{
+    Params P;
+    int npl, threads;
+    size_t lds;
+    if (!make_params(pb, pl, lambda, false, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
+    P.H = H; P.y = y;
+    P.g_in = g; P.dinv_in = dinv; P.p_in = p;
+    P.z = reinterpret_cast<float2 *>(z);
+    P.llr = llr;
+    P.z_hist = reinterpret_cast<float2 *>(z_hist);
+    set_vec_ok(P, pb, H, y);
+    hipError_t e = launch_forward(pl.lanes_per_vector, npl, pb->storage == OCD_STORE_F16, P,
+                                  threads, lds, stream);
+    return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_detect(const ocd_problem *pb, const void *H, const void *y,
+                                 const float *lambda, const float *g, const float *dinv,
+                                 const float *p, float *z, float *llr, float *z_hist,
+                                 hipStream_t stream)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    const int given = (g != nullptr) + (dinv != nullptr) + (p != nullptr);
+    if (given != 0 && given != 3) return OCD_EINVAL;
+    if (pb->W == 0) return OCD_OK;
+    if (!H || !y) return OCD_EINVAL;
+    const ocd_plan pl = choose_plan(pb, lambda, false);
+    return run_forward(pb, pl, H, y, lambda, g, dinv, p, z, llr, z_hist, stream);
+}
+
+extern "C" ocd_status ocd_get_plan(const ocd_problem *pb, ocd_plan *plan)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!plan) return OCD_EINVAL;
+    *plan = choose_plan(pb, nullptr, false);
+    return OCD_OK;
+}
+
+extern "C" ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!plan) return OCD_EINVAL;
+    Params P;
+    int npl, threads;
+    size_t lds;
+    if (!make_params(pb, *plan, nullptr, false, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
+    store_plan(plan_key(pb, false, false), *plan, false);
+    return OCD_OK;
+}
+
+extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y, float *z,
+                                   float *llr, int repeats, ocd_plan *best, hipStream_t stream)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!H || !y || !z || !llr || !best) return OCD_EINVAL;
+    if (pb->W == 0) {
+        *best = heuristic_plan(pb, nullptr, false);
+        return OCD_OK;
+    }
+    repeats = std::max(1, std::min(repeats, 100));
+    std::vector<ocd_plan> cands;
+    for (int L : {4, 8, 16, 32}) {
+        const int cap = 512 / L;
+        std::vector<int> vs;
+        for (int v = cap; v >= 1 && v >= cap / 16; v /= 2) vs.push_back(v);
+        if (pb->S > 1)   // whole subcarriers per workgroup: one LDS slot per subcarrier
+            for (int m = pb->S; m <= cap && m <= 4 * pb->S; m += pb->S) vs.push_back(m);
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        for (int v : vs)
+            for (int x : {0, 1}) {
+                ocd_plan pl = {L, v, x, 0};
+                Params P;
+                int npl, threads;
+                size_t lds;
+                if (make_params(pb, pl, nullptr, false, P, npl, threads, lds)) cands.push_back(pl);
+            }
+    }
+    if (cands.empty()) return OCD_EUNSUPPORTED;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return OCD_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OCD_EDEVICE; }
+    float best_ms = 1e30f;
+    ocd_plan best_pl = cands[0];
+    st = OCD_OK;
+    for (const ocd_plan &pl : cands) {
+        st = run_forward(pb, pl, H, y, nullptr, nullptr, nullptr, nullptr, z, llr, nullptr, stream);
+        if (st != OCD_OK) break;
+        (void)hipEventRecord(e0, stream);
+        for (int i = 0; i < repeats && st == OCD_OK; ++i)
+            st = run_forward(pb, pl, H, y, nullptr, nullptr, nullptr, nullptr, z, llr, nullptr, stream);
+        (void)hipEventRecord(e1, stream);
+        if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) { st = OCD_EDEVICE; break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best_pl = pl; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != OCD_OK) return st;
+    store_plan(plan_key(pb, false, false), best_pl, true);
+    *best = best_pl;
+    return OCD_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+
+extern "C" size_t ocd_backward_workspace_bytes(const ocd_problem *pb)
+{
+    if (validate(pb) != OCD_OK) return 0;
+    // block partials of (dlambda_1..K, dbeta) for the plan with the most blocks
+    const long nvec = (long)pb->W * pb->S;
+    return (size_t)std::max(1L, nvec) * (size_t)(pb->K + 1) * sizeof(float) + 256;
+}
+
+extern "C" ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void *y,
+                                          const float *lambda, const float *z_hist,
+                                          const float *dllr, float *dlambda, float *dbeta,
+                                          float *dy, void *workspace, size_t workspace_bytes,
+                                          hipStream_t stream)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!dlambda || !dbeta) return OCD_EINVAL;
+    if (pb->W > 0 && (!H || !y || !z_hist || !dllr)) return OCD_EINVAL;
+    if (workspace_bytes < ocd_backward_workspace_bytes(pb) || !workspace) return OCD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return OCD_EINVAL;
+    const ocd_plan pl = choose_plan(pb, lambda, true);
+    Params P;
+    int npl, threads;
+    size_t lds;
+    if (!make_params(pb, pl, lambda, true, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
+    P.H = H; P.y = y;
+    P.zh_in = reinterpret_cast<const float2 *>(z_hist);
+    P.dllr = dllr;
+    P.dy = reinterpret_cast<float2 *>(dy);
+    P.partials = reinterpret_cast<float *>(workspace);
+    set_vec_ok(P, pb, H, y);
+    hipError_t e = hipSuccess;
+    if (pb->W > 0)
+        e = launch_backward(pl.lanes_per_vector, npl, pb->storage == OCD_STORE_F16, P, threads,
+                            lds, stream);
+    if (e == hipSuccess) {
+        if (pb->W == 0) P.nblocks = 0;
+        e = launch_reduce_partials(P, dlambda, dbeta, stream);
+    }
+    return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}

@@ -1,0 +1,28 @@
+// ocd_api_internal.h -- host helpers shared by the ABI translation units.
+#pragma once
+
+#include <string>
+
+#include "../../include/ocd.h"
+#include "ocd_internal.h"
+
+namespace ocd {
+
+ocd_status validate(const ocd_problem *pb);
+std::string arch_name();
+int lds_limit_bytes();
+float box_edge(int Q);
+int npl_for(int B, int L);
+bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda, bool backward,
+                 Params &P, int &npl, int &threads, size_t &lds);
+void set_vec_ok(Params &P, const ocd_problem *pb, const void *H, const void *y);
+ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backward);
+ocd_plan choose_plan(const ocd_problem *pb, const float *lambda, bool backward);
+std::string plan_key(const ocd_problem *pb, bool per_sweep, bool backward);
+bool cached_plan(const std::string &key, ocd_plan &pl);
+void store_plan(const std::string &key, const ocd_plan &pl, bool persist);
+ocd_status run_forward(const ocd_problem *pb, const ocd_plan &pl, const void *H, const void *y,
+                       const float *lambda, const float *g, const float *dinv, const float *p,
+                       float *z, float *llr, float *z_hist, hipStream_t stream);
+
+}  // namespace ocd

@@ -1,0 +1,255 @@
+// ocd_backward.hip -- adjoint of Algorithm 1 plus the soft output.
+//
+// Per vector the kernel rebuilds the final residual r^(K) = y - H z^(K) from the
+// stored history, seeds dLoss/dz from dLoss/dLLR through the max-log LLR, and
+// then walks the K*U coordinate updates backwards.  For the update (k, u):
+//   forward   c = d^-1 h^H r_pre + p z_old,  z_new = proj(c),
+//             r_post = r_pre - h (z_new - z_old)
+//   reverse   r_pre  = r_post + h (z_new - z_old)           (recomputed, not stored)
+//             Delta_bar = -h^H r_bar,  t = z_bar + Delta_bar
+//             c_bar = t on unclipped parts, 0 on clipped ones (those add sign(c) t to beta_bar)
+//             lambda_bar_k += -d^-2 Re(conj(h^H r_pre) c_bar) - g d^-2 Re(conj(z_old) c_bar)
+//             z_bar = -Delta_bar + p c_bar,  r_bar += h d^-1 c_bar
+// y_bar is r_bar after the first update.  Each update costs three lane-local
+// complex dot/axpy passes plus one 4-float all-reduce, about twice the forward.
+// Per-sweep and box partial sums go to a per-workgroup slot of the workspace
+// and are reduced in a fixed order by k_reduce_partials.
+#include "ocd_stage.h"
+
+namespace ocd {
+
+// dLoss/dz of one user from dLoss/dLLR through L_b = rho * D_b(x), x = z/(mu sqrt(Es)),
+// and the contribution of mu(lambda_K), rho(lambda_K) to dLoss/dlambda_K.
+template <int HALF>
+__device__ __forceinline__ void user_llr_adjoint(const float *Lbar, float xr, float xi, float s,
+                                                 float mu, float rho, float scale, float2 *zbar,
+                                                 float *dmu, float *drho)
+{
+    float Dr[HALF], Di[HALF];
+    axis_llr<HALF>(xr, scale, 1.0f, Dr);
+    axis_llr<HALF>(xi, scale, 1.0f, Di);
+    float xbr = 0.f, xbi = 0.f, gm = 0.f, gr = 0.f;
+#pragma unroll
+    for (int bb = 0; bb < HALF; ++bb) {
+        const float sr = axis_llr_slope<HALF>(xr, scale, bb);
+        const float si = axis_llr_slope<HALF>(xi, scale, bb);
+        const float lr = Lbar[bb], li = Lbar[HALF + bb];
+        xbr = fmaf(lr * rho, sr, xbr);
+        xbi = fmaf(li * rho, si, xbi);
+        gr = fmaf(lr, Dr[bb], fmaf(li, Di[bb], gr));
+        // dx/dmu = -x/mu
+        gm = fmaf(lr * rho * sr, -xr / mu, gm);
+        gm = fmaf(li * rho * si, -xi / mu, gm);
+    }
+    *zbar = make_float2(xbr * s, xbi * s);
+    *dmu = gm;
+    *drho = gr;
+}
+
+template <int L, int NPL, bool F16, bool BOX>
+__global__ __launch_bounds__(512) void k_backward(Params P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int U = P.U, K = P.K, Bpad = P.Bpad;
+    const int Kt = P.per_sweep ? K : 1;
+    const int vpb_cap = blockDim.x / L;
+    const Smem sm = carve(smem, P, vpb_cap, true);
+    const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const Tile t = tile_of(P, bid);
+
+    stage_subcarriers<F16>(P, sm, t.w_first, t.nslots);
+
+    const int grp = threadIdx.x / L, j = threadIdx.x % L;
+    const bool active = grp < t.nvb;
+    const long v = t.vbase + (active ? grp : 0);
+    const int slot = (int)(v / P.S) - t.w_first;
+    const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
+    const float2 *dps = sm.dp + (size_t)slot * Kt * U;
+    const float *gs = sm.g + (size_t)slot * U;
+    float2 *zv = sm.z + (size_t)grp * U;
+    float2 *zp = sm.zprev + (size_t)grp * U;
+    float2 *zb = sm.zbar + (size_t)grp * U;
+    const float2 *zh = P.zh_in + v * K * U;
+
+    // z^(K) and the final residual r^(K) = y - H z^(K)
+    for (int u = 0; u < U; ++u)
+        zv[u] = active ? zh[(size_t)(K - 1) * U + u] : make_float2(0.f, 0.f);
+    float2 r[NPL];
+    load_vector<L, NPL, F16>(P, P.y, v, j, active, r);
+    for (int u = 0; u < U; ++u) {
+        float2 h[NPL];
+        load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
+        axpy_sub<NPL>(h, zv[u], r);
+    }
+
+    // soft-output adjoint, one owner lane per user
+    const float lamK = P.lambda ? P.lambda[K - 1] : P.lam_default;
+    const float2 *dpK = dps + (P.per_sweep ? K - 1 : 0) * U;
+    const float sqEs = sqrtf(P.Es), scale = qam_scale(P.Q);
+    float lamK_bar = 0.f;
+    for (int u = j; u < U; u += L) {
+        float2 zbar = make_float2(0.f, 0.f);
+        const float gu = gs[u];
+        float mu, rho;
+        gain_sinr(P, lamK, gu, dpK[u].y, &mu, &rho);
+        if (active && rho > 0.f && mu > 0.f) {
+            const float s = 1.0f / (mu * sqEs);
+            const float2 zu = zv[u];
+            const float *Lbar = P.dllr + (v * U + u) * P.Q;
+            float dmu = 0.f, drho = 0.f;
+            if (P.Q == 2) user_llr_adjoint<1>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
+            else if (P.Q == 4) user_llr_adjoint<2>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
+            else user_llr_adjoint<3>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
+            if (lamK > 0.f) {
+                const float dK = dpK[u].x;   // (g + lambda_K)^-1
+                lamK_bar = fmaf(drho, -gu / (lamK * lamK), lamK_bar);
+                lamK_bar = fmaf(dmu, -gu * dK * dK, lamK_bar);
+            }
+        }
+        zb[u] = zbar;
+    }
+    lamK_bar = group_sum<L>(lamK_bar);
+
+    float2 rb[NPL];
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) rb[i] = make_float2(0.f, 0.f);
+    const float beta = P.beta;
+    float beta_bar = 0.f;
+    float *part_out = P.partials + (size_t)bid * (K + 1);
+
+    for (int k = K - 1; k >= 0; --k) {
+        for (int u = j; u < U; u += L)
+            zp[u] = (k > 0 && active) ? zh[(size_t)(k - 1) * U + u] : make_float2(0.f, 0.f);
+        __syncthreads();   // z_prev and z_bar rows written by their owner lanes
+        const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
+        float lam_bar = (k == K - 1) ? lamK_bar : 0.f;
+        for (int u = U - 1; u >= 0; --u) {
+            float2 h[NPL];
+            load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
+            const float2 znew = zv[u], zold = zp[u];
+            axpy_add<NPL>(h, make_float2(znew.x - zold.x, znew.y - zold.y), r);   // r_pre
+            float2 ip = partial_inner<NPL>(h, r);
+            float2 hb = partial_inner<NPL>(h, rb);
+            ip.x = group_sum<L>(ip.x);
+            ip.y = group_sum<L>(ip.y);
+            hb.x = group_sum<L>(hb.x);
+            hb.y = group_sum<L>(hb.y);
+            const float2 dp = dpk[u];
+            const float cr = fmaf(dp.x, ip.x, dp.y * zold.x);
+            const float ci = fmaf(dp.x, ip.y, dp.y * zold.y);
+            const float2 zbu = zb[u];
+            const float tr = zbu.x - hb.x, ti = zbu.y - hb.y;   // z_bar + Delta_bar
+            float cbr = tr, cbi = ti;
+            if constexpr (BOX) {
+                if (fabsf(cr) > beta) { beta_bar += cr > 0.f ? tr : -tr; cbr = 0.f; }
+                if (fabsf(ci) > beta) { beta_bar += ci > 0.f ? ti : -ti; cbi = 0.f; }
+            }
+            const float d2 = dp.x * dp.x;
+            lam_bar = fmaf(-d2, fmaf(ip.x, cbr, ip.y * cbi), lam_bar);
+            lam_bar = fmaf(-gs[u] * d2, fmaf(zold.x, cbr, zold.y * cbi), lam_bar);
+            zb[u] = make_float2(hb.x + dp.y * cbr, hb.y + dp.y * cbi);   // -Delta_bar + p c_bar
+            zv[u] = zold;
+            axpy_add<NPL>(h, make_float2(dp.x * cbr, dp.x * cbi), rb);
+        }
+        if (j == 0) sm.part[grp] = active ? lam_bar : 0.f;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float s = 0.f;
+            for (int g = 0; g < vpb_cap; ++g) s += sm.part[g];
+            part_out[k] = s;
+        }
+        __syncthreads();
+    }
+    if (j == 0) sm.part[grp] = active ? beta_bar : 0.f;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int g = 0; g < vpb_cap; ++g) s += sm.part[g];
+        part_out[K] = s;
+    }
+    if (active && P.dy) {
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int b = lane_antenna(j, i, L, 2);
+            if (b < P.B) P.dy[v * P.B + b] = rb[i];
+        }
+    }
+}
+
+// Sums the per-workgroup partials in a fixed order: thread t adds workgroups
+// t, t + 256, ... sequentially, then a fixed tree over the 256 threads.
+__global__ __launch_bounds__(256) void k_reduce_partials(const float *partials, int nblocks, int K,
+                                                         int box, float *dlambda, float *dbeta)
+{
+    __shared__ float red[256];
+    const int e = blockIdx.x;   // 0..K-1: dlambda, K: dbeta
+    float s = 0.f;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(size_t)b * (K + 1) + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (e < K) dlambda[e] = red[0];
+        else *dbeta = box ? red[0] : 0.f;
+    }
+}
+
+template <int L, int NPL, bool F16, bool BOX>
+static hipError_t launch_bwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
+{
+    auto fn = k_backward<L, NPL, F16, BOX>;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(p.nblocks), dim3(threads), lds, s, p);
+    return hipGetLastError();
+}
+
+template <int L, int NPL>
+static hipError_t launch_bwd_ln(bool f16, const Params &p, int threads, size_t lds, hipStream_t s)
+{
+    if (f16) return p.box ? launch_bwd_t<L, NPL, true, true>(p, threads, lds, s)
+                          : launch_bwd_t<L, NPL, true, false>(p, threads, lds, s);
+    return p.box ? launch_bwd_t<L, NPL, false, true>(p, threads, lds, s)
+                 : launch_bwd_t<L, NPL, false, false>(p, threads, lds, s);
+}
+
+template <int L>
+static hipError_t launch_bwd_l(int NPL, bool f16, const Params &p, int threads, size_t lds,
+                               hipStream_t s)
+{
+    switch (NPL) {
+    case 2: return launch_bwd_ln<L, 2>(f16, p, threads, lds, s);
+    case 4: return launch_bwd_ln<L, 4>(f16, p, threads, lds, s);
+    case 8: return launch_bwd_ln<L, 8>(f16, p, threads, lds, s);
+    case 16: return launch_bwd_ln<L, 16>(f16, p, threads, lds, s);
+    case 32: return launch_bwd_ln<L, 32>(f16, p, threads, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_backward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
+                           hipStream_t s)
+{
+    switch (L) {
+    case 4: return launch_bwd_l<4>(NPL, f16, p, threads, lds, s);
+    case 8: return launch_bwd_l<8>(NPL, f16, p, threads, lds, s);
+    case 16: return launch_bwd_l<16>(NPL, f16, p, threads, lds, s);
+    case 32: return launch_bwd_l<32>(NPL, f16, p, threads, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_partials, dim3(p.K + 1), dim3(256), 0, s, p.partials, p.nblocks,
+                       p.K, p.box, dlambda, dbeta);
+    return hipGetLastError();
+}
+
+}  // namespace ocd

@@ -1,0 +1,191 @@
+// ocd_device.h -- device-side building blocks of the OCD detector (gfx950).
+//
+// A (subcarrier, symbol) vector is owned by a group of L consecutive lanes of
+// one wavefront.  Lane j of the group holds NPL of the B receive entries,
+// in chunks of CH consecutive antennas: entry i of the lane is antenna
+//   b = CH * (j + L * (i / CH)) + i % CH
+// so that a group reads whole contiguous rows of y and of the H columns.
+// Antennas b >= B are zero padding (they add nothing to any inner product
+// and are never updated).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace ocd {
+
+// ------------------------------------------------------------------ layout
+
+template <int NPL, bool F16>
+struct Layout {
+    // complex entries per contiguous chunk of one lane
+    static constexpr int CH = NPL < 2 ? NPL : 2;
+    static constexpr int NCH = NPL / CH;
+};
+
+__device__ __forceinline__ int lane_antenna(int j, int i, int L, int CH)
+{
+    return CH * (j + L * (i / CH)) + i % CH;
+}
+
+// ------------------------------------------------------------------ cross-lane sums
+
+// DPP control words (GFX9 encoding).
+enum : int {
+    DPP_QUAD_XOR1 = 0xB1,  // quad_perm [1,0,3,2]
+    DPP_QUAD_XOR2 = 0x4E,  // quad_perm [2,3,0,1]
+    DPP_ROW_MIRROR = 0x140,
+    DPP_ROW_HALF_MIRROR = 0x141,
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_get(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the L lanes of an aligned group; every lane of the group receives
+// the same bits (each level adds a commutative pair).  L <= 16 stays in DPP
+// row operations; 32 and 64 add a swizzle / permute across rows.
+template <int L>
+__device__ __forceinline__ float group_sum(float x)
+{
+    if constexpr (L >= 2) x += dpp_get<DPP_QUAD_XOR1>(x);
+    if constexpr (L >= 4) x += dpp_get<DPP_QUAD_XOR2>(x);
+    if constexpr (L >= 8) x += dpp_get<DPP_ROW_HALF_MIRROR>(x);
+    if constexpr (L >= 16) x += dpp_get<DPP_ROW_MIRROR>(x);
+    if constexpr (L >= 32)  // lane ^ 16 within 32 lanes: ds_swizzle bit-mask mode
+        x += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(x), 0x401F));
+    if constexpr (L >= 64) {
+        int src = (static_cast<int>(__lane_id()) ^ 32) << 2;
+        x += __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(x)));
+    }
+    return x;
+}
+
+// Full-wavefront sum (64 lanes), identical in every lane.
+__device__ __forceinline__ float wave_sum(float x) { return group_sum<64>(x); }
+
+// ------------------------------------------------------------------ loads
+
+__device__ __forceinline__ float2 half2_to_float2(uint32_t bits)
+{
+    __half2 h = *reinterpret_cast<const __half2 *>(&bits);
+    return __half22float2(h);
+}
+
+// Load `n` consecutive complex entries starting at element `e` of a row,
+// converting to FP32; entries at or beyond `limit` read as zero.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+template <bool F16, int N>
+__device__ __forceinline__ void load_chunk(const void *base, long e, int b, int limit, bool vec_ok,
+                                           float2 *out)
+{
+    if (vec_ok && b + N <= limit) {
+        if constexpr (!F16) {
+            const float2 *p = reinterpret_cast<const float2 *>(base) + e;
+            if constexpr (N == 2) {
+                f32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(p));
+                out[0] = make_float2(q.x, q.y);
+                out[1] = make_float2(q.z, q.w);
+            } else {
+                for (int t = 0; t < N; ++t) out[t] = p[t];
+            }
+        } else {
+            const uint32_t *p = reinterpret_cast<const uint32_t *>(base) + e;
+            if constexpr (N == 2) {
+                u32x2_t q = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t *>(p));
+                out[0] = half2_to_float2(q.x);
+                out[1] = half2_to_float2(q.y);
+            } else {
+                for (int t = 0; t < N; ++t) out[t] = half2_to_float2(p[t]);
+            }
+        }
+        return;
+    }
+    for (int t = 0; t < N; ++t) {
+        if (b + t < limit) {
+            if constexpr (!F16) out[t] = reinterpret_cast<const float2 *>(base)[e + t];
+            else out[t] = half2_to_float2(reinterpret_cast<const uint32_t *>(base)[e + t]);
+        } else {
+            out[t] = make_float2(0.f, 0.f);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ soft output
+
+// Max-log LLRs of one axis of Gray square QAM (HALF = Q/2 bits per axis):
+// L_b = rho * (min over levels whose label bit b is 0 of (x - A)^2
+//            - min over levels whose label bit b is 1 of (x - A)^2).
+// Levels A_m = (2m - M + 1) * scale, label of level m = m ^ (m >> 1), MSB first.
+// For a product constellation the other axis' minimum is common to both sets
+// and cancels, so this equals the two-dimensional minimum of the definition.
+template <int HALF>
+__device__ __forceinline__ void axis_llr(float xc, float scale, float rho, float *out)
+{
+    constexpr int M = 1 << HALF;
+    float d[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float e = xc - (float)(2 * m - M + 1) * scale;
+        d[m] = e * e;
+    }
+#pragma unroll
+    for (int bb = 0; bb < HALF; ++bb) {
+        float d0 = INFINITY, d1 = INFINITY;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int bit = ((m ^ (m >> 1)) >> (HALF - 1 - bb)) & 1;
+            if (bit) d1 = fminf(d1, d[m]);
+            else d0 = fminf(d0, d[m]);
+        }
+        out[bb] = rho * (d0 - d1);
+    }
+}
+
+// Index of the level nearest to xc among the two minimisers used for bit bb
+// (first minimiser in level order on ties); returns the adjoint factor
+// dD/dxc = 2 (A_{m1} - A_{m0}) for D = (xc - A_{m0})^2 - (xc - A_{m1})^2.
+template <int HALF>
+__device__ __forceinline__ float axis_llr_slope(float xc, float scale, int bb)
+{
+    constexpr int M = 1 << HALF;
+    float d0 = INFINITY, d1 = INFINITY;
+    int m0 = 0, m1 = 0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        float e = xc - (float)(2 * m - M + 1) * scale;
+        float dm = e * e;
+        const int bit = ((m ^ (m >> 1)) >> (HALF - 1 - bb)) & 1;
+        if (bit) {
+            if (dm < d1) { d1 = dm; m1 = m; }
+        } else {
+            if (dm < d0) { d0 = dm; m0 = m; }
+        }
+    }
+    return 2.0f * (float)(2 * (m1 - m0)) * scale;
+}
+
+// Square-QAM level spacing for unit average energy: 1 / sqrt(2 (M^2 - 1) / 3).
+__host__ __device__ inline float qam_scale(int Q)
+{
+    const int M = 1 << (Q / 2);
+    return 1.0f / sqrtf(2.0f * (float)(M * M - 1) / 3.0f);
+}
+
+// ------------------------------------------------------------------ block mapping
+
+// Permutes block ids so that consecutive tiles land on the same XCD (blocks are
+// dispatched round-robin over the 8 XCDs, each with its own L2).
+__device__ __forceinline__ int xcd_tile(int bx, int nblocks)
+{
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int xcd = bx & 7, idx = bx >> 3;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+}  // namespace ocd

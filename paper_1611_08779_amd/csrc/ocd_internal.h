@@ -1,0 +1,67 @@
+// ocd_internal.h -- launch parameters shared by the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ocd {
+
+// Everything a forward or backward launch needs, by value.
+struct Params {
+    int B, U, W, S, K, Q;
+    int box;         // projection onto the box is active (BOX, HYBRID)
+    int per_sweep;   // a per-sweep regulariser array was given: dinv, p are [Kt = K][U]
+    int Bpad;        // L * NPL >= B
+    int vpb;         // vectors per workgroup
+    int maxslots;    // LDS slots for distinct subcarriers per workgroup
+    int slot_stride; // float2 elements between slots (padded)
+    int xcd_remap;
+    int vec_ok;      // vector loads allowed (B even, 16-byte aligned bases)
+    int nblocks;
+    float Es, N0, beta;
+    float lam_default;   // regulariser when lambda == nullptr
+    const float *lambda; // device [K] or nullptr
+    const void *H;       // [W][U][B] complex (FP32 or FP16 pairs)
+    const void *y;       // [W][S][B]
+    const float *g_in;   // [W][U] or nullptr (then preprocessing is fused)
+    const float *dinv_in;// [W][Kt][U]
+    const float *p_in;   // [W][Kt][U]
+    float2 *z;           // [W][S][U] or nullptr
+    float *llr;          // [W][S][U][Q] or nullptr
+    float2 *z_hist;      // [W][S][K][U] or nullptr
+    // backward only
+    const float2 *zh_in; // [W][S][K][U]
+    const float *dllr;   // [W][S][U][Q]
+    float2 *dy;          // [W][S][B] or nullptr
+    float *partials;     // [nblocks][K + 1]
+};
+
+// Bytes of dynamic LDS a launch of this shape needs.
+inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward)
+{
+    const int Kt = p.per_sweep ? p.K : 1;
+    size_t b = 0;
+    b += (size_t)p.maxslots * p.slot_stride * 8;     // H slots (FP32 complex)
+    b += (size_t)p.maxslots * p.U * 4;               // g
+    b = (b + 7) & ~(size_t)7;
+    b += (size_t)p.maxslots * Kt * p.U * 8;          // (dinv, p) pairs
+    b += (size_t)vpb_cap * p.U * 8;                  // z per vector
+    if (backward) {
+        b += (size_t)vpb_cap * p.U * 8;              // z^(k-1) row per vector
+        b += (size_t)vpb_cap * p.U * 8;              // z_bar per vector
+        b += (size_t)vpb_cap * 4 * 2;                // per-group partials
+    }
+    return b;
+}
+
+// Launchers (one per template instantiation, selected at run time).
+hipError_t launch_forward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
+                          hipStream_t s);
+hipError_t launch_backward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
+                           hipStream_t s);
+hipError_t launch_preprocess(bool f16, const Params &p, float *g, float *dinv, float *pp,
+                             hipStream_t s);
+hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s);
+
+}  // namespace ocd

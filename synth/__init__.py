@@ -149,3 +149,37 @@ def batched_job_list(n_jobs: int = 48, seed: int = 4) -> list[dict]:
             S=14, Q=6, snr_db=20.0, seed=[4, j],
         ))
     return jobs
+
+
+def make_workload_device(B: int, U: int, W: int, S: int, Q: int, snr_db: float, seed: int,
+                         Es: float = 1.0, device="cuda"):
+    """The same model as :func:`make_workload`, drawn with torch's seeded RNG on the
+    device (for the large benchmark workloads).  Returns a dict with ``H``
+    complex64 ``[W,U,B]``, ``y`` complex64 ``[W,S,B]``, ``bits`` uint8
+    ``[W,S,U,Q]`` (device tensors) and ``N0``.  ``y = H s + n`` is formed in
+    complex64 on the device."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    N0 = n0_from_snr(snr_db, Es)
+    sd = math.sqrt(0.5 / B)
+
+    def cn(shape, std):
+        re = torch.randn(shape, generator=gen, device=device, dtype=torch.float32) * std
+        im = torch.randn(shape, generator=gen, device=device, dtype=torch.float32) * std
+        return torch.complex(re, im)
+
+    H = cn((W, U, B), sd)
+    bits = torch.randint(0, 2, (W, S, U, Q), generator=gen, device=device, dtype=torch.uint8)
+    half = Q // 2
+    M = 1 << half
+    amp = torch.tensor(_axis_amplitudes(M), device=device, dtype=torch.float32)
+    lvl = torch.tensor(_label_to_level(M), device=device, dtype=torch.long)
+    weights = torch.tensor([1 << (half - 1 - i) for i in range(half)], device=device,
+                           dtype=torch.long)
+    lab_i = (bits[..., :half].long() * weights).sum(-1)
+    lab_q = (bits[..., half:].long() * weights).sum(-1)
+    s = math.sqrt(Es) * torch.complex(amp[lvl[lab_i]], amp[lvl[lab_q]])        # [W,S,U]
+    y = torch.matmul(s, H.contiguous()) + cn((W, S, B), math.sqrt(0.5 * N0))     # [W,S,B]
+    return {"H": H.contiguous(), "y": y.contiguous(), "bits": bits, "N0": N0, "Es": float(Es)}

@@ -1,0 +1,123 @@
+"""The C ABI without a GPU: libocd.so loads, exports every function declared in
+include/ocd.h, and rejects invalid problems before touching the device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ocd.h")
+LIB = os.path.join(ROOT, "paper_1611_08779_amd", "libocd.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1611_08779_amd import build as b
+        b.build()
+    return ctypes.CDLL(LIB)
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(ocd_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("ocd_preprocess", "ocd_detect", "ocd_detect_backward", "ocd_detect_jobs",
+                     "ocd_autotune", "ocd_status_str"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_python_binding_names_match_the_header():
+    import paper_1611_08779_amd as ocd
+    for name in _declared_functions():
+        assert callable(getattr(ocd, name)), name
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int), ("U", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int),
+                ("Q", ctypes.c_int), ("K", ctypes.c_int), ("mode", ctypes.c_int),
+                ("storage", ctypes.c_int), ("N0", ctypes.c_float), ("Es", ctypes.c_float),
+                ("beta", ctypes.c_float)]
+
+
+def _good():
+    return dict(B=128, U=8, W=1200, S=14, Q=6, K=3, mode=0, storage=0, N0=0.01, Es=1.0, beta=0.0)
+
+
+BAD = [
+    dict(B=0), dict(B=1025), dict(U=0), dict(U=33), dict(B=4, U=5), dict(W=-1), dict(S=0),
+    dict(Q=3), dict(Q=8), dict(K=0), dict(K=257), dict(mode=3), dict(storage=2),
+    dict(N0=0.0), dict(N0=-1.0), dict(N0=float("nan")), dict(Es=0.0), dict(Es=float("inf")),
+    dict(beta=float("nan")),
+]
+
+
+@pytest.mark.parametrize("bad", BAD, ids=[str(b) for b in BAD])
+def test_invalid_problems_are_rejected_before_any_launch(lib, bad):
+    kw = _good()
+    kw.update(bad)
+    pb = Problem(**kw)
+    lib.ocd_detect.restype = ctypes.c_int
+    lib.ocd_detect.argtypes = [ctypes.POINTER(Problem)] + [ctypes.c_void_p] * 10
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    st = lib.ocd_detect(ctypes.byref(pb), dummy, dummy, None, None, None, None, dummy, dummy,
+                        None, None)
+    assert st == -1
+
+
+def test_status_strings_and_version(lib):
+    lib.ocd_status_str.restype = ctypes.c_char_p
+    assert lib.ocd_status_str(0) == b"OCD_OK"
+    assert b"EINVAL" in lib.ocd_status_str(-1)
+    assert b"EUNSUPPORTED" in lib.ocd_status_str(-2)
+    assert b"EDEVICE" in lib.ocd_status_str(-3)
+    assert lib.ocd_version() >= 10000
+
+
+def test_partial_preprocessing_arguments_are_rejected(lib):
+    pb = Problem(**_good())
+    lib.ocd_detect.restype = ctypes.c_int
+    lib.ocd_detect.argtypes = [ctypes.POINTER(Problem)] + [ctypes.c_void_p] * 10
+    d = ctypes.c_void_p(0x1000)
+    # g given without dinv and p
+    assert lib.ocd_detect(ctypes.byref(pb), d, d, None, d, None, None, d, d, None, None) == -1
+
+
+def test_backward_workspace_size_and_null_checks(lib):
+    pb = Problem(**_good())
+    lib.ocd_backward_workspace_bytes.restype = ctypes.c_size_t
+    lib.ocd_backward_workspace_bytes.argtypes = [ctypes.POINTER(Problem)]
+    n = lib.ocd_backward_workspace_bytes(ctypes.byref(pb))
+    assert n >= 1200 * 14 * 4 * 4
+    bad = Problem(**dict(_good(), K=0))
+    assert lib.ocd_backward_workspace_bytes(ctypes.byref(bad)) == 0
+    lib.ocd_detect_backward.restype = ctypes.c_int
+    lib.ocd_detect_backward.argtypes = ([ctypes.POINTER(Problem)] + [ctypes.c_void_p] * 8 +
+                                        [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p])
+    d = ctypes.c_void_p(0x1000)
+    # missing dlambda
+    assert lib.ocd_detect_backward(ctypes.byref(pb), d, d, None, d, d, None, d, d, d, n, None) == -1
+    # workspace too small
+    assert lib.ocd_detect_backward(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, 16, None) == -1
+
+
+def test_jobs_rejects_null_arguments(lib):
+    lib.ocd_detect_jobs.restype = ctypes.c_int
+    lib.ocd_detect_jobs.argtypes = [ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    pb = Problem(**_good())
+    assert lib.ocd_detect_jobs(ctypes.byref(pb), None, None, None, None, 1, None, 0, 0, None) == -1
+    assert lib.ocd_detect_jobs(ctypes.byref(pb), None, None, None, None, 0, None, 0, 0, None) == -1

@@ -1,0 +1,149 @@
+"""GPU parity of the adjoint kernel (ocd_detect_backward) and of the autograd
+wrapper: gradients of the bit cross-entropy of the LLRs with respect to the
+per-sweep regularisers, the box half-width and y, against the FP64 oracle's
+reverse mode and against FP64 central differences of the oracle's forward pass;
+relative L2 error within 1e-3 for each gradient."""
+
+import numpy as np
+import pytest
+import scipy.special
+import torch
+
+import oracle
+import synth
+from gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def ocd():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1611_08779_amd as m
+    return m
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.complex128).ravel(), np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _bce(L, bits):
+    return float(np.mean(np.logaddexp(0.0, L) - bits * L))
+
+
+def _case(ocd, mode, B=128, U=16, W=32, S=4, Q=4, K=4, snr=10.0, seed=0):
+    """Config-5 slice: 32 subcarriers x 4 symbols, 16-QAM, K=4, 10 dB."""
+    say("backward case mode=%s B=%d U=%d W=%d S=%d Q=%d K=%d" % (mode, B, U, W, S, Q, K))
+    wl = synth.make_workload(B, U, W, S, Q, snr, seed=[20, seed])
+    N0 = f32(wl["N0"])
+    lam = np.full(K, N0, np.float32) * np.array([1.0, 0.8, 1.3, 0.9, 1.1, 1.0][:K], np.float32) \
+        if mode == "hybrid" else None
+    beta = f32(0.9 * 3 / np.sqrt(10)) if mode != "mmse" else 0.0
+    H, y = dev(wl["H"]), dev(wl["y"])
+    lam_t = dev(lam) if lam is not None else None
+    _, L, zh = ocd.detect(H, y, K, Q, mode, N0, 1.0, beta, lam=lam_t, want_z=False, want_hist=True)
+    bits = torch.from_numpy(wl["bits"]).cuda().float()
+    dllr = (torch.sigmoid(L) - bits) / bits.numel()
+    dlam, dbeta, dy = ocd.backward(H, y, zh, dllr, K, Q, mode, N0, 1.0, beta, lam=lam_t)
+    torch.cuda.synchronize()
+    return dict(wl=wl, N0=N0, lam=lam, beta=beta, K=K, Q=Q, L=host(L), dllr=host(dllr),
+                dlam=host(dlam), dbeta=float(host(dbeta)[0]), dy=host(dy), H=H, y=y, zh=zh,
+                lam_t=lam_t, dllr_t=dllr)
+
+
+@pytest.mark.parametrize("mode", ["hybrid", "box", "mmse"])
+def test_adjoint_matches_oracle_reverse_mode(ocd, mode):
+    c = _case(ocd, mode)
+    wl = c["wl"]
+    dlam_o, dbeta_o, dy_o = oracle.grad(wl["H"], wl["y"], c["dllr"].astype(np.float64), c["K"],
+                                        c["Q"], mode, N0=c["N0"], lam=c["lam"], beta=c["beta"])
+    say("  dlam gpu", c["dlam"], "oracle", dlam_o)
+    say("  dbeta gpu %.6g oracle %.6g" % (c["dbeta"], dbeta_o))
+    assert rel(c["dlam"], dlam_o) <= GRAD_TOL
+    assert rel(c["dy"], dy_o) <= GRAD_TOL
+    if mode == "mmse":
+        assert c["dbeta"] == 0.0
+    else:
+        assert dbeta_o != 0.0
+        assert abs(c["dbeta"] - dbeta_o) <= GRAD_TOL * abs(dbeta_o)
+
+
+def test_adjoint_matches_fp64_finite_differences(ocd):
+    """dLoss/dlambda_k and dLoss/dbeta against central differences of the FP64 oracle's
+    loss (LLRs from oracle.ocd + oracle.llr, bit cross-entropy)."""
+    c = _case(ocd, "hybrid", seed=1)
+    wl = c["wl"]
+    H, y, bits = wl["H"].astype(np.complex128), wl["y"].astype(np.complex128), wl["bits"]
+    K, Q, N0 = c["K"], c["Q"], c["N0"]
+
+    def loss(lam, beta):
+        z = oracle.ocd(H, y, K, Q, "hybrid", N0=N0, lam=lam, beta=beta, threads=0)
+        return _bce(oracle.llr(H, z, K, Q, "hybrid", N0=N0, lam=lam, beta=beta, threads=0), bits)
+
+    lam0 = c["lam"].astype(np.float64)
+    fd = []
+    for k in range(K):
+        h = 1e-5 * lam0[k]
+        lp, lm = lam0.copy(), lam0.copy()
+        lp[k] += h
+        lm[k] -= h
+        fd.append((loss(lp, c["beta"]) - loss(lm, c["beta"])) / (2 * h))
+    hb = 1e-6
+    fdb = (loss(lam0, c["beta"] + hb) - loss(lam0, c["beta"] - hb)) / (2 * hb)
+    say("  fd dlam", np.array(fd), "gpu", c["dlam"])
+    say("  fd dbeta %.6g gpu %.6g" % (fdb, c["dbeta"]))
+    assert rel(c["dlam"], fd) <= 5e-3   # FD over 2048 users crosses a few clip/argmin kinks
+    assert abs(c["dbeta"] - fdb) <= 5e-3 * abs(fdb)
+
+
+def test_adjoint_is_bitwise_reproducible(ocd):
+    c = _case(ocd, "hybrid", W=16, seed=2)
+    d2 = ocd.backward(c["H"], c["y"], c["zh"], c["dllr_t"], c["K"], c["Q"], "hybrid", c["N0"], 1.0,
+                      c["beta"], lam=c["lam_t"])
+    torch.cuda.synchronize()
+    assert np.array_equal(host(d2[0]), c["dlam"])
+    assert np.array_equal(host(d2[2]), c["dy"])
+
+
+@pytest.mark.parametrize("case", [(33, 5, 7, 3, 6, 2, "box"), (256, 32, 4, 14, 2, 3, "hybrid"),
+                                  (16, 4, 3, 1, 4, 9, "mmse")])
+def test_adjoint_edge_shapes(ocd, case):
+    B, U, W, S, Q, K, mode = case
+    c = _case(ocd, mode, B, U, W, S, Q, K, 8.0, seed=3)
+    wl = c["wl"]
+    dlam_o, dbeta_o, dy_o = oracle.grad(wl["H"], wl["y"], c["dllr"].astype(np.float64), K, Q, mode,
+                                        N0=c["N0"], lam=c["lam"], beta=c["beta"])
+    assert rel(c["dlam"], dlam_o) <= GRAD_TOL
+    assert rel(c["dy"], dy_o) <= GRAD_TOL
+    if mode != "mmse" and dbeta_o != 0.0:
+        assert abs(c["dbeta"] - dbeta_o) <= GRAD_TOL * abs(dbeta_o)
+
+
+def test_autograd_function_drives_the_kernels(ocd):
+    from paper_1611_08779_amd.autograd import ocd_llr
+    B, U, W, S, Q, K = 128, 16, 16, 4, 4, 4
+    wl = synth.make_workload(B, U, W, S, Q, 10.0, seed=[21, 0])
+    N0 = f32(wl["N0"])
+    H = dev(wl["H"])
+    y = dev(wl["y"]).requires_grad_(True)
+    lam = torch.full((K,), N0, device="cuda", requires_grad=True)
+    beta = torch.tensor([3 / np.sqrt(10)], device="cuda", dtype=torch.float32, requires_grad=True)
+    L = ocd_llr(y, H, K, Q, "hybrid", N0, 1.0, lam, beta)
+    bits = torch.from_numpy(wl["bits"]).cuda().float()
+    loss = torch.nn.functional.binary_cross_entropy_with_logits(L, bits)
+    loss.backward()
+    torch.cuda.synchronize()
+    dlam_o, dbeta_o, dy_o = oracle.grad(wl["H"], wl["y"],
+                                        host((torch.sigmoid(L) - bits) / bits.numel()).astype(np.float64),
+                                        K, Q, "hybrid", N0=N0, lam=host(lam.detach()),
+                                        beta=float(host(beta.detach())[0]))
+    assert rel(host(lam.grad), dlam_o) <= GRAD_TOL
+    assert rel(host(y.grad), dy_o) <= GRAD_TOL
+    assert abs(float(host(beta.grad)[0]) - dbeta_o) <= GRAD_TOL * max(abs(dbeta_o), 1e-12)

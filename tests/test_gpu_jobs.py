@@ -1,0 +1,111 @@
+"""GPU parity of the batched persistent launch (ocd_detect_jobs): every job against
+the FP64 oracle and bit-for-bit against a one-problem launch with the same lane
+split; graph replays checked against the eager result on every replay."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import (LLR_TOL_F32, Z_TOL_F32, dev, host, llr_rel_err, oracle_ref, say, to_f16_pairs,
+                      z_rel_err)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ocd():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1611_08779_amd as m
+    return m
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+# uneven shapes drawn like the 48-job batch, cut down so the oracle stays fast
+JOBS = [
+    (64, 4, 21, 2), (128, 8, 30, 3), (256, 32, 5, 4), (128, 16, 11, 2), (64, 32, 9, 3),
+    (256, 4, 17, 2), (128, 32, 3, 4), (64, 8, 40, 3), (256, 16, 7, 2), (33, 5, 6, 3),
+]
+
+
+def _make(ocd, storage="f32", jobs=JOBS, S=14, Q=6):
+    probs, Hs, ys, wls = [], [], [], []
+    for j, (B, U, W, K) in enumerate(jobs):
+        wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[30, j])
+        N0 = f32(wl["N0"])
+        probs.append(ocd.problem(B, U, W, S, Q, K, "mmse", storage, N0))
+        if storage == "f16":
+            Hs.append(dev(to_f16_pairs(wl["H"])))
+            ys.append(dev(to_f16_pairs(wl["y"])))
+        else:
+            Hs.append(dev(wl["H"]))
+            ys.append(dev(wl["y"]))
+        wls.append(wl)
+    return probs, Hs, ys, wls
+
+
+def _lanes(B):
+    L = 4
+    while 16 * L < B:
+        L *= 2
+    return L
+
+
+def test_jobs_match_oracle_and_single_launches(ocd):
+    probs, Hs, ys, wls = _make(ocd)
+    say("jobs: %d uneven problems" % len(probs))
+    z, L, ws = ocd.detect_jobs(probs, Hs, ys)
+    torch.cuda.synchronize()
+    for j, (pb, wl) in enumerate(zip(probs, wls)):
+        zo, Lo, _ = oracle_ref(wl["H"], wl["y"], pb.K, pb.Q, "mmse", pb.N0)
+        assert z_rel_err(host(z[j]), zo) <= Z_TOL_F32, j
+        assert llr_rel_err(host(L[j]), Lo) <= LLR_TOL_F32, j
+        # same lane split and 16 entries per lane as the batched kernel: same bits
+        ocd.ocd_set_plan(pb, ocd.Plan(_lanes(pb.B), 14, 0, 0))
+        z1, L1, _ = ocd.detect(Hs[j], ys[j], pb.K, pb.Q, "mmse", pb.N0)
+        torch.cuda.synchronize()
+        assert torch.equal(z1, z[j]) and torch.equal(L1, L[j]), j
+
+
+def test_jobs_graph_replays_match_eager(ocd):
+    probs, Hs, ys, wls = _make(ocd)
+    z0, L0, ws = ocd.detect_jobs(probs, Hs, ys)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        z = [torch.full_like(t, float("nan")) for t in z0]
+        L = [torch.full_like(t, float("nan")) for t in L0]
+        ocd.ocd_detect_jobs(probs, Hs, ys, z, L, ws, flags=ocd.OCD_JOBS_GRAPH)
+        torch.cuda.synchronize()
+        # eager work and a synchronisation between replays
+        _ = ocd.detect(Hs[1], ys[1], probs[1].K, probs[1].Q, "mmse", probs[1].N0)
+        torch.cuda.synchronize()
+        for j in range(len(probs)):
+            assert torch.equal(z[j], z0[j]) and torch.equal(L[j], L0[j]), (rep, j)
+
+
+def test_jobs_graph_follows_new_buffers(ocd):
+    """The graph reads job pointers from the workspace tables: new output buffers on a
+    replay must be the ones written."""
+    probs, Hs, ys, _ = _make(ocd)
+    z0, L0, ws = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_GRAPH)
+    torch.cuda.synchronize()
+    z1, L1, _ = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_GRAPH, workspace=ws)
+    torch.cuda.synchronize()
+    for j in range(len(probs)):
+        assert torch.equal(z1[j], z0[j]) and torch.equal(L1[j], L0[j])
+
+
+def test_jobs_tuner_and_fp16_storage(ocd):
+    probs, Hs, ys, wls = _make(ocd, storage="f16", jobs=JOBS[:5])
+    z, L, ws = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_TUNE)
+    torch.cuda.synchronize()
+    from gpu_util import from_f16_pairs
+    for j, (pb, wl) in enumerate(zip(probs, wls)):
+        zo, Lo, _ = oracle_ref(from_f16_pairs(host(Hs[j])), from_f16_pairs(host(ys[j])), pb.K, pb.Q,
+                               "mmse", pb.N0)
+        assert z_rel_err(host(z[j]), zo) <= Z_TOL_F32, j
+        assert llr_rel_err(host(L[j]), Lo) <= LLR_TOL_F32, j
+    ocd.ocd_release_graphs()
