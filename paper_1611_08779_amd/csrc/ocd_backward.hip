@@ -57,25 +57,32 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const Tile t = tile_of(P, bid);
 
-    stage_subcarriers<F16>(P, sm, t.w_first, t.nslots);
-
     const int grp = threadIdx.x / L, j = threadIdx.x % L;
     const bool active = grp < t.nvb;
-    const long v = t.vbase + (active ? grp : 0);
-    const int slot = (int)(v / P.S) - t.w_first;
+    const int v = t.vbase + (active ? grp : 0);
+    const int slot = v / P.S - t.w_first;
+
+    // H_w chunk loads, then y, then the LDS stores of H (see forward_tile)
+    const int chunks = t.nslots * U * (Bpad >> 1);
+    float4 hbuf[STAGE_CHUNKS];
+    stage_h_load<F16>(P, t.w_first, chunks, 0, hbuf);
+    float2 r[NPL];
+    load_vector<L, NPL, F16>(P, P.y, v, j, active, r);
+    stage_h_store(P, sm, chunks, 0, hbuf);
+    stage_h_copy<F16>(P, sm, t.w_first, chunks, STAGE_CHUNKS * (int)blockDim.x);
+    stage_preprocess(P, sm, t.w_first, t.nslots);
+    clear_padding<L, NPL>(P, j, active, r);
     const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
     const float2 *dps = sm.dp + (size_t)slot * Kt * U;
     const float *gs = sm.g + (size_t)slot * U;
     float2 *zv = sm.z + (size_t)grp * U;
     float2 *zp = sm.zprev + (size_t)grp * U;
     float2 *zb = sm.zbar + (size_t)grp * U;
-    const float2 *zh = P.zh_in + v * K * U;
+    const float2 *zh = P.zh_in + (long)v * K * U;
 
     // z^(K) and the final residual r^(K) = y - H z^(K)
     for (int u = 0; u < U; ++u)
         zv[u] = active ? zh[(size_t)(K - 1) * U + u] : make_float2(0.f, 0.f);
-    float2 r[NPL];
-    load_vector<L, NPL, F16>(P, P.y, v, j, active, r);
     for (int u = 0; u < U; ++u) {
         float2 h[NPL];
         load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
@@ -95,7 +102,7 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
         if (active && rho > 0.f && mu > 0.f) {
             const float s = 1.0f / (mu * sqEs);
             const float2 zu = zv[u];
-            const float *Lbar = P.dllr + (v * U + u) * P.Q;
+            const float *Lbar = P.dllr + ((long)v * U + u) * P.Q;
             float dmu = 0.f, drho = 0.f;
             if (P.Q == 2) user_llr_adjoint<1>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
             else if (P.Q == 4) user_llr_adjoint<2>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
 #pragma unroll
         for (int i = 0; i < NPL; ++i) {
             const int b = lane_antenna(j, i, L, 2);
-            if (b < P.B) P.dy[v * P.B + b] = rb[i];
+            if (b < P.B) P.dy[(long)v * P.B + b] = rb[i];
         }
     }
 }

@@ -75,10 +75,29 @@ __device__ __forceinline__ float2 half2_to_float2(uint32_t bits)
     return __half22float2(h);
 }
 
-// Load `n` consecutive complex entries starting at element `e` of a row,
-// converting to FP32; entries at or beyond `limit` read as zero.
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+// Two consecutive complex entries at element e (aligned: e even), FP32 out.
+// No branch: the caller passes an address that is always valid and selects.
+template <bool F16>
+__device__ __forceinline__ float4 load_pair(const void *base, long e)
+{
+    if constexpr (!F16) {
+        const f32x4_t q = __builtin_nontemporal_load(
+            reinterpret_cast<const f32x4_t *>(reinterpret_cast<const float2 *>(base) + e));
+        return make_float4(q.x, q.y, q.z, q.w);
+    } else {
+        const u32x2_t q = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x2_t *>(reinterpret_cast<const uint32_t *>(base) + e));
+        const float2 a = half2_to_float2(q.x), b = half2_to_float2(q.y);
+        return make_float4(a.x, a.y, b.x, b.y);
+    }
+}
+
+// Load `N` consecutive complex entries starting at element `e` of a row,
+// converting to FP32; entries at or beyond `limit` read as zero.  General
+// (branchy) path, used where vector loads are not allowed.
 
 template <bool F16, int N>
 __device__ __forceinline__ void load_chunk(const void *base, long e, int b, int limit, bool vec_ok,

@@ -34,9 +34,10 @@ struct JobDesc {
 };
 
 struct TileDesc {
-    long vbase;
+    int vbase;
     int job;
     int nvb;
+    int pad_;
 };
 
 constexpr size_t HEADER_BYTES = 256;
@@ -59,8 +60,8 @@ __global__ __launch_bounds__(JOB_THREADS) void k_jobs(const JobDesc *jobs, const
         Tile t;
         t.vbase = td.vbase;
         t.nvb = td.nvb;
-        t.w_first = (int)(td.vbase / P.S);
-        t.nslots = (int)((td.vbase + td.nvb - 1) / P.S) - t.w_first + 1;
+        t.w_first = td.vbase / P.S;
+        t.nslots = (td.vbase + td.nvb - 1) / P.S - t.w_first + 1;
         switch (jd.L) {
         case 4: forward_tile<4, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 4, false), t); break;
         case 8: forward_tile<8, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 8, false), t); break;
@@ -136,9 +137,10 @@ static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, JobsPlan
         const long nvec = (long)pb->W * pb->S;
         for (long v = 0; v < nvec; v += P.vpb) {
             TileDesc td;
-            td.vbase = v;
+            td.vbase = (int)v;
             td.job = j;
             td.nvb = (int)std::min<long>(P.vpb, nvec - v);
+            td.pad_ = 0;
             out.tiles.push_back(td);
         }
     }

@@ -46,44 +46,105 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const Params &P, int 
 
 // The vectors of one workgroup: [vbase, vbase + nvb) in (subcarrier, symbol)
 // order; they touch subcarriers w_first .. w_first + nslots - 1.
+// Vector indices fit in 32 bits (W * S <= 2^30 is checked on the host).
 struct Tile {
-    long vbase;
+    int vbase;
     int nvb, w_first, nslots;
 };
 
 __device__ __forceinline__ Tile tile_of(const Params &P, int bid)
 {
     Tile t;
-    const long nvec = (long)P.W * P.S;
-    t.vbase = (long)bid * P.vpb;
-    long rem = nvec - t.vbase;
-    t.nvb = (int)(rem < P.vpb ? rem : P.vpb);
-    t.w_first = (int)(t.vbase / P.S);
-    t.nslots = (int)((t.vbase + t.nvb - 1) / P.S) - t.w_first + 1;
+    const int nvec = P.W * P.S;
+    t.vbase = bid * P.vpb;
+    const int rem = nvec - t.vbase;
+    t.nvb = rem < P.vpb ? rem : P.vpb;
+    t.w_first = t.vbase / P.S;
+    t.nslots = (t.vbase + t.nvb - 1) / P.S - t.w_first + 1;
     return t;
 }
 
-// Copies H_w of every touched subcarrier into LDS (FP32, zero padded to Bpad)
-// and computes Algorithm 1's preprocessing once per subcarrier:
-// g_u = ||h_u||^2, d_u^-1 = (g_u + lambda_k)^-1 (0 if that is 1/0), p_u = d_u^-1 g_u.
-// Ends with a workgroup barrier.
+// Copy of H_w into LDS in two halves, so that the caller can put other global
+// loads (its receive vectors) in flight between them: stage_h_load issues the
+// loads of up to STAGE_CHUNKS chunks (two complex entries each) per thread into
+// registers, stage_h_store writes them to LDS (FP32, zero padded to Bpad).  Chunk
+// c of a tile is row c / (Bpad/2) (the rows of the touched subcarriers are
+// consecutive in [W][U][B]) and antennas 2 (c mod Bpad/2) and the next one.
+constexpr int STAGE_CHUNKS = 4;
+
 template <bool F16>
-__device__ void stage_subcarriers(const Params &P, const Smem &sm, int w_first, int nslots)
+__device__ __forceinline__ void stage_h_load(const Params &P, int w_first, int total, int c0,
+                                             float4 (&buf)[STAGE_CHUNKS])
 {
-    const int U = P.U, B = P.B, Bpad = P.Bpad;
+    const int half = P.Bpad >> 1;
+    const int sh = __ffs(half) - 1;   // Bpad is a power of two
+    const long rbase = (long)w_first * P.U;
+    if (P.vec_ok) {
+        // B even: a chunk is wholly inside or wholly outside the row.  Out-of-range
+        // chunks load a valid address and are replaced by zeros, so no load sits
+        // behind a branch and all of them are in flight together.
+#pragma unroll
+        for (int i = 0; i < STAGE_CHUNKS; ++i) {
+            const int c = c0 + i * (int)blockDim.x + (int)threadIdx.x;
+            const int row = c >> sh, b = (c & (half - 1)) << 1;
+            const bool ok = c < total && b < P.B;
+            buf[i] = load_pair<F16>(P.H, ok ? (rbase + row) * P.B + b : 0);
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < STAGE_CHUNKS; ++i) {
+        const int c = c0 + i * (int)blockDim.x + (int)threadIdx.x;
+        float2 v[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        if (c < total) {
+            const int row = c >> sh, b = (c & (half - 1)) << 1;
+            load_chunk<F16, 2>(P.H, (rbase + row) * P.B + b, b, P.B, false, v);
+        }
+        buf[i] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    }
+}
+
+__device__ __forceinline__ void stage_h_store(const Params &P, const Smem &sm, int total, int c0,
+                                              const float4 (&buf)[STAGE_CHUNKS])
+{
+    const int half = P.Bpad >> 1;
+    const int sh = __ffs(half) - 1;
+    const int gap = P.slot_stride - P.U * P.Bpad;   // padding between LDS slots
+#pragma unroll
+    for (int i = 0; i < STAGE_CHUNKS; ++i) {
+        const int c = c0 + i * (int)blockDim.x + (int)threadIdx.x;
+        if (c < total) {
+            const int row = c >> sh, b = (c & (half - 1)) << 1;
+            const int slot = row / P.U;
+            // antennas past B (loaded from a placeholder address) become zero padding
+            const float4 q = b < P.B ? buf[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            *reinterpret_cast<float4 *>(sm.H + (size_t)row * P.Bpad + (size_t)slot * gap + b) = q;
+        }
+    }
+}
+
+// Copies H_w of every touched subcarrier into LDS (all passes).
+template <bool F16>
+__device__ __forceinline__ void stage_h_copy(const Params &P, const Smem &sm, int w_first,
+                                             int total, int c0)
+{
+    for (; c0 < total; c0 += STAGE_CHUNKS * (int)blockDim.x) {
+        float4 buf[STAGE_CHUNKS];
+        stage_h_load<F16>(P, w_first, total, c0, buf);
+        stage_h_store(P, sm, total, c0, buf);
+    }
+}
+
+// Algorithm 1's preprocessing once per staged subcarrier (or a copy of the
+// precomputed values): g_u = ||h_u||^2, d_u^-1 = (g_u + lambda_k)^-1 (0 if that
+// is 1/0), p_u = d_u^-1 g_u.  Ends with a workgroup barrier, after which the
+// staged H_w is visible to every thread.
+__device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, int nslots)
+{
+    const int U = P.U, Bpad = P.Bpad;
     const int Kt = P.per_sweep ? P.K : 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
     const int rows = nslots * U;
-    for (int row = wave; row < rows; row += nwaves) {
-        const int slot = row / U, u = row - slot * U;
-        const long e0 = ((long)(w_first + slot) * U + u) * B;
-        float2 *dst = sm.H + (size_t)slot * P.slot_stride + (size_t)u * Bpad;
-        for (int b = 2 * lane; b < Bpad; b += 128) {
-            float2 v[2];
-            load_chunk<F16, 2>(P.H, e0 + b, b, B, P.vec_ok != 0, v);
-            *reinterpret_cast<float4 *>(dst + b) = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-        }
-    }
     if (P.g_in) {
         for (int i = threadIdx.x; i < rows; i += blockDim.x)
             sm.g[i] = P.g_in[(long)w_first * U + i];
@@ -112,16 +173,51 @@ __device__ void stage_subcarriers(const Params &P, const Smem &sm, int w_first, 
     __syncthreads();
 }
 
-// Loads this lane's NPL receive entries of vector v (zeros when inactive).
+// H_w copy and preprocessing in one go (for callers with nothing to overlap).
+template <bool F16>
+__device__ void stage_subcarriers(const Params &P, const Smem &sm, int w_first, int nslots)
+{
+    stage_h_copy<F16>(P, sm, w_first, nslots * P.U * (P.Bpad >> 1), 0);
+    stage_preprocess(P, sm, w_first, nslots);
+}
+
+// Loads this lane's NPL receive entries of vector v.  On the vector path the
+// loads are branch-free and nothing reads them here, so they stay in flight
+// while the caller stages H; antennas past B and idle groups load a placeholder
+// address and must be cleared with clear_padding() before first use.
 template <int L, int NPL, bool F16>
-__device__ __forceinline__ void load_vector(const Params &P, const void *base, long v, int j,
+__device__ __forceinline__ void load_vector(const Params &P, const void *base, int v, int j,
                                             bool active, float2 *r)
 {
+    if (P.vec_ok) {
+#pragma unroll
+        for (int c = 0; c < NPL / 2; ++c) {
+            const int b = 2 * (j + L * c);
+            const bool ok = active && b < P.B;
+            const float4 q = load_pair<F16>(base, ok ? (long)v * P.B + b : 0);
+            r[2 * c] = make_float2(q.x, q.y);
+            r[2 * c + 1] = make_float2(q.z, q.w);
+        }
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < NPL / 2; ++c) {
         const int b = 2 * (j + L * c);
-        if (active) load_chunk<F16, 2>(base, v * P.B + b, b, P.B, P.vec_ok != 0, &r[2 * c]);
+        if (active) load_chunk<F16, 2>(base, (long)v * P.B + b, b, P.B, false, &r[2 * c]);
         else r[2 * c] = r[2 * c + 1] = make_float2(0.f, 0.f);
+    }
+}
+
+// Zeroes the entries load_vector filled from placeholder addresses.
+template <int L, int NPL>
+__device__ __forceinline__ void clear_padding(const Params &P, int j, bool active, float2 *r)
+{
+    if (!P.vec_ok) return;
+#pragma unroll
+    for (int c = 0; c < NPL / 2; ++c) {
+        const bool ok = active && 2 * (j + L * c) < P.B;
+        r[2 * c] = ok ? r[2 * c] : make_float2(0.f, 0.f);
+        r[2 * c + 1] = ok ? r[2 * c + 1] : make_float2(0.f, 0.f);
     }
 }
 
@@ -180,6 +276,26 @@ __device__ __forceinline__ void axpy_add(const float2 *h, float2 a, float2 *r)
         r[i].y = fmaf(h[i].x, a.y, r[i].y);
         r[i].y = fmaf(h[i].y, a.x, r[i].y);
     }
+}
+
+// One coordinate update of Algorithm 1 for the lanes of a group:
+//   z_u' = proj(d_u^-1 h_u^H r + p_u z_u),  r <- r - h_u (z_u' - z_u).
+// h: this lane's part of column u; dp = (d_u^-1, p_u); zo = z_u.  Returns z_u'.
+template <int L, int NPL, bool BOX>
+__device__ __forceinline__ float2 coordinate_update(const float2 *h, float2 dp, float2 zo,
+                                                    float beta, float2 *r)
+{
+    float2 ip = partial_inner<NPL>(h, r);
+    ip.x = group_sum<L>(ip.x);
+    ip.y = group_sum<L>(ip.y);
+    float cr = fmaf(dp.x, ip.x, dp.y * zo.x);
+    float ci = fmaf(dp.x, ip.y, dp.y * zo.y);
+    if constexpr (BOX) {
+        cr = fminf(fmaxf(cr, -beta), beta);
+        ci = fminf(fmaxf(ci, -beta), beta);
+    }
+    axpy_sub<NPL>(h, make_float2(cr - zo.x, ci - zo.y), r);
+    return make_float2(cr, ci);
 }
 
 // Section III-C: approximate channel gain mu = d^-1 g (= p of the last sweep) and

@@ -29,50 +29,48 @@ __device__ __forceinline__ void user_llr(float xr, float xi, float scale, float 
 // threads of idle lane groups may return before the others finish, so a caller
 // that reuses the LDS for another tile must synchronise first.
 template <int L, int NPL, bool F16, bool BOX>
-__device__ void forward_tile(const Params &P, const Smem &sm, const Tile &t)
+__device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
 {
     const int U = P.U, Bpad = P.Bpad;
     const int Kt = P.per_sweep ? P.K : 1;
 
-    stage_subcarriers<F16>(P, sm, t.w_first, t.nslots);
-
     const int grp = threadIdx.x / L, j = threadIdx.x % L;
-    const bool active = grp < t.nvb;
-    const long v = t.vbase + (active ? grp : 0);
-    const int slot = (int)(v / P.S) - t.w_first;
+    const bool active = grp < tile.nvb;
+    const int v = tile.vbase + (active ? grp : 0);
+    const int slot = v / P.S - tile.w_first;
+
+    // H_w chunk loads first, then the receive vector (initialisation r = y):
+    // both global round trips are in flight together, and the LDS stores of H
+    // wait only for the H chunks.
+    const int chunks = tile.nslots * U * (Bpad >> 1);
+    float4 hbuf[STAGE_CHUNKS];
+    stage_h_load<F16>(P, tile.w_first, chunks, 0, hbuf);
+    float2 r[NPL];
+    load_vector<L, NPL, F16>(P, P.y, v, j, active, r);
+    stage_h_store(P, sm, chunks, 0, hbuf);
+    stage_h_copy<F16>(P, sm, tile.w_first, chunks, STAGE_CHUNKS * (int)blockDim.x);
+    stage_preprocess(P, sm, tile.w_first, tile.nslots);
+    clear_padding<L, NPL>(P, j, active, r);
+
     const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
     const float2 *dps = sm.dp + (size_t)slot * Kt * U;
     float2 *zv = sm.z + (size_t)grp * U;
+    for (int u = 0; u < U; ++u) zv[u] = make_float2(0.f, 0.f);   // z^(0) = 0
 
-    // initialisation: r = y, z = 0
-    float2 r[NPL];
-    load_vector<L, NPL, F16>(P, P.y, v, j, active, r);
-    for (int u = 0; u < U; ++u) zv[u] = make_float2(0.f, 0.f);
-
+    // K sweeps over the users in order (Alg. 1); with several waves per SIMD
+    // the LDS latency of each update is hidden by the other waves.
     const float beta = P.beta;
     for (int k = 0; k < P.K; ++k) {
         const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
         for (int u = 0; u < U; ++u) {
             float2 h[NPL];
             load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
-            float2 ip = partial_inner<NPL>(h, r);
-            ip.x = group_sum<L>(ip.x);
-            ip.y = group_sum<L>(ip.y);
             const float2 dp = dpk[u];
             const float2 zo = zv[u];
-            // z_u = proj(d_u^-1 h_u^H r + p_u z_u)
-            float cr = fmaf(dp.x, ip.x, dp.y * zo.x);
-            float ci = fmaf(dp.x, ip.y, dp.y * zo.y);
-            if constexpr (BOX) {
-                cr = fminf(fmaxf(cr, -beta), beta);
-                ci = fminf(fmaxf(ci, -beta), beta);
-            }
-            zv[u] = make_float2(cr, ci);
-            // r <- r - h_u (z_u^(k) - z_u^(k-1))
-            axpy_sub<NPL>(h, make_float2(cr - zo.x, ci - zo.y), r);
+            zv[u] = coordinate_update<L, NPL, BOX>(h, dp, zo, beta, r);
         }
         if (P.z_hist && active)
-            for (int u = j; u < U; u += L) P.z_hist[(v * P.K + k) * U + u] = zv[u];
+            for (int u = j; u < U; u += L) P.z_hist[((long)v * P.K + k) * U + u] = zv[u];
     }
 
     if (!active) return;
@@ -81,7 +79,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &t)
     const float sqEs = sqrtf(P.Es), scale = qam_scale(P.Q);
     for (int u = j; u < U; u += L) {
         const float2 zu = zv[u];
-        if (P.z) P.z[v * U + u] = zu;
+        if (P.z) P.z[(long)v * U + u] = zu;
         if (!P.llr) continue;
         float mu, rho;
         gain_sinr(P, lamK, sm.g[slot * U + u], dpK[u].y, &mu, &rho);
@@ -93,7 +91,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &t)
             else if (P.Q == 4) user_llr<2>(xr, xi, scale, rho, out);
             else user_llr<3>(xr, xi, scale, rho, out);
         }
-        float *dst = P.llr + (v * U + u) * P.Q;
+        float *dst = P.llr + ((long)v * U + u) * P.Q;
         for (int b = 0; b < P.Q; ++b) dst[b] = out[b];
     }
 }
