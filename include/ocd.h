@@ -160,26 +160,31 @@ ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
 ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,
                         float *z, float *llr, int repeats, ocd_plan *best, hipStream_t stream);
 
-/* Batched detection of uneven jobs in one persistent launch.
+/* Batched detection of uneven jobs in one launch.
  * Each job j is a full problem (jobs[j]) with its own device arrays H[j], y[j],
  * z[j] (may be NULL) and llr[j] (may be NULL); every job must use the default
- * regulariser (lambda = NULL) and the same storage.  Jobs are cut into tiles,
- * ordered longest-first, and persistent workgroups pop tiles from a device
- * queue until it is empty.
+ * regulariser (lambda = NULL), the same storage and the same projection (MMSE,
+ * or BOX/HYBRID), and B <= 256.  Jobs are cut into tiles of whole subcarriers,
+ * ordered longest-first (LPT), and run by one launch of one kernel: either one
+ * workgroup per tile (the hardware dispatcher balances them) or persistent
+ * workgroups that pop tiles from a device queue until it is empty.
  *   workspace   device, >= ocd_jobs_workspace_bytes(jobs, n_jobs), 256-byte aligned;
- *               holds the tile table and the queue head.
- *   flags       OCD_JOBS_GRAPH: capture {queue reset, persistent kernel} in a
- *               hipGraph on the first call for this workspace and replay it on
- *               later calls with the same job list (pointers are read from the
- *               workspace, so only the table is re-uploaded when they change).
- *               OCD_JOBS_TUNE: before running, time every tile-size policy on the
- *               caller's buffers (outputs are overwritten; synchronises `stream`)
- *               and keep the fastest for this list of job shapes.
- * The call enqueues a host-to-device copy of the tile table from pinned memory
- * held by the library and waits for the previous upload from the same
- * workspace, so it may block until earlier work on `stream` has consumed it. */
+ *               holds the job and tile tables and the queue head.
+ *   flags       OCD_JOBS_GRAPH: capture the launch (queue reset and kernel) in a
+ *               hipGraph on the first call for this workspace and job list, and
+ *               replay it afterwards (job pointers are read from the workspace,
+ *               so a change of pointers only re-uploads the tables).
+ *               OCD_JOBS_TUNE: before running, time every schedule and tile-size
+ *               policy on the caller's buffers (outputs are overwritten;
+ *               synchronises `stream`) and keep the fastest for this list of shapes.
+ *               OCD_JOBS_PERSISTENT: use the persistent schedule.
+ * When the tables change, the call enqueues a host-to-device copy of them from
+ * pinned memory held by the library and first waits for the previous copy from
+ * the same workspace, so it may block until earlier work on `stream` consumed
+ * it.  Calls that share a workspace must be ordered on one stream. */
 #define OCD_JOBS_GRAPH 1
 #define OCD_JOBS_TUNE 2
+#define OCD_JOBS_PERSISTENT 4
 size_t ocd_jobs_workspace_bytes(const ocd_problem *jobs, int n_jobs);
 ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const *H, const void *const *y,
                            float *const *z, float *const *llr, int n_jobs,

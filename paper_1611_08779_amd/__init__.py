@@ -33,6 +33,7 @@ __all__ = [
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_get_plan", "ocd_set_plan",
     "ocd_autotune", "ocd_jobs_workspace_bytes", "ocd_detect_jobs", "ocd_release_graphs",
     "problem", "detect", "preprocess", "backward", "detect_jobs", "OCD_JOBS_GRAPH", "OCD_JOBS_TUNE",
+    "OCD_JOBS_PERSISTENT", "JobsCall",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,6 +43,7 @@ MODES = {"mmse": 0, "box": 1, "hybrid": 2}
 STORAGES = {"f32": 0, "f16": 1}
 OCD_JOBS_GRAPH = 1
 OCD_JOBS_TUNE = 2
+OCD_JOBS_PERSISTENT = 4
 
 _STATUS = {0: "OCD_OK", -1: "OCD_EINVAL", -2: "OCD_EUNSUPPORTED", -3: "OCD_EDEVICE"}
 
@@ -257,28 +259,45 @@ def ocd_jobs_workspace_bytes(jobs) -> int:
     return int(_lib.ocd_jobs_workspace_bytes(arr, len(jobs)))
 
 
+class JobsCall:
+    """Arguments of ``ocd_detect_jobs`` marshalled once, for repeated launches on the
+    same buffers (the batched form is meant to be replayed; checking 4 tensors per
+    job on every call would cost more host time than the launch)."""
+
+    def __init__(self, jobs, H, y, z, llr, workspace, flags=0):
+        n = len(jobs)
+        self.n = n
+        self.arr = _problem_array(jobs)
+        self.ptrs = [(ctypes.c_void_p * n)() for _ in range(4)]
+        dev = H[0].device
+        for j, pb in enumerate(jobs):
+            self.ptrs[0][j] = _dev_ptr(H[j], "H[%d]" % j, _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb), dev)
+            self.ptrs[1][j] = _dev_ptr(y[j], "y[%d]" % j, _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev)
+            self.ptrs[2][j] = _dev_ptr(z[j] if z is not None else None, "z[%d]" % j,
+                                       (torch.complex64, torch.float32), pb.W * pb.S * pb.U * 8, dev)
+            self.ptrs[3][j] = _dev_ptr(llr[j] if llr is not None else None, "llr[%d]" % j,
+                                       (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev)
+        self.ws_need = ocd_jobs_workspace_bytes(jobs)
+        if self.ws_need == 0:
+            raise OCDError("ocd_jobs_workspace_bytes", -1)
+        self.wsp = _dev_ptr(workspace, "workspace", (torch.uint8,), self.ws_need, dev)
+        if self.wsp % 256:
+            raise ValueError("workspace must be 256-byte aligned")
+        self.has_z, self.has_llr = z is not None, llr is not None
+        self.flags = int(flags)
+        self._keep = (H, y, z, llr, workspace)   # the buffers must outlive the call object
+
+    def __call__(self, flags=None, stream=None):
+        st = _lib.ocd_detect_jobs(self.arr, self.ptrs[0], self.ptrs[1],
+                                  self.ptrs[2] if self.has_z else None,
+                                  self.ptrs[3] if self.has_llr else None, self.n, self.wsp,
+                                  self.ws_need, self.flags if flags is None else int(flags),
+                                  _stream(stream))
+        _check("ocd_detect_jobs", st)
+
+
 def ocd_detect_jobs(jobs, H, y, z, llr, workspace, flags=0, stream=None) -> None:
-    n = len(jobs)
-    arr = _problem_array(jobs)
-    ptrs = [(ctypes.c_void_p * n)() for _ in range(4)]
-    dev = H[0].device
-    for j, pb in enumerate(jobs):
-        ptrs[0][j] = _dev_ptr(H[j], "H[%d]" % j, _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb), dev)
-        ptrs[1][j] = _dev_ptr(y[j], "y[%d]" % j, _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev)
-        ptrs[2][j] = _dev_ptr(z[j] if z is not None else None, "z[%d]" % j,
-                              (torch.complex64, torch.float32), pb.W * pb.S * pb.U * 8, dev)
-        ptrs[3][j] = _dev_ptr(llr[j] if llr is not None else None, "llr[%d]" % j,
-                              (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev)
-    ws_need = ocd_jobs_workspace_bytes(jobs)
-    if ws_need == 0:
-        raise OCDError("ocd_jobs_workspace_bytes", -1)
-    wsp = _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev)
-    if wsp % 256:
-        raise ValueError("workspace must be 256-byte aligned")
-    st = _lib.ocd_detect_jobs(arr, ptrs[0], ptrs[1], ptrs[2] if z is not None else None,
-                              ptrs[3] if llr is not None else None, n, wsp, ws_need, int(flags),
-                              _stream(stream))
-    _check("ocd_detect_jobs", st)
+    JobsCall(jobs, H, y, z, llr, workspace, flags)(stream=stream)
 
 
 def ocd_release_graphs() -> None:

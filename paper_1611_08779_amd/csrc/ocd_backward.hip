@@ -75,9 +75,10 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
     const float2 *dps = sm.dp + (size_t)slot * Kt * U;
     const float *gs = sm.g + (size_t)slot * U;
-    float2 *zv = sm.z + (size_t)grp * U;
-    float2 *zp = sm.zprev + (size_t)grp * U;
-    float2 *zb = sm.zbar + (size_t)grp * U;
+    const int zr = zrow_of(P, grp);
+    float2 *zv = sm.z + (size_t)zr * U;
+    float2 *zp = sm.zprev + (size_t)zr * U;
+    float2 *zb = sm.zbar + (size_t)zr * U;
     const float2 *zh = P.zh_in + (long)v * K * U;
 
     // z^(K) and the final residual r^(K) = y - H z^(K)

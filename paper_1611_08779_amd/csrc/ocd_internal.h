@@ -46,11 +46,11 @@ inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward)
     b += (size_t)p.maxslots * p.U * 4;               // g
     b = (b + 7) & ~(size_t)7;
     b += (size_t)p.maxslots * Kt * p.U * 8;          // (dinv, p) pairs
-    b += (size_t)vpb_cap * p.U * 8;                  // z per vector
+    b += (size_t)(p.vpb + 1) * p.U * 8;              // z per vector (+ idle groups' row)
     if (backward) {
-        b += (size_t)vpb_cap * p.U * 8;              // z^(k-1) row per vector
-        b += (size_t)vpb_cap * p.U * 8;              // z_bar per vector
-        b += (size_t)vpb_cap * 4 * 2;                // per-group partials
+        b += (size_t)(p.vpb + 1) * p.U * 8;          // z^(k-1) row per vector
+        b += (size_t)(p.vpb + 1) * p.U * 8;          // z_bar per vector
+        b += (size_t)vpb_cap * 4;                    // per-group partials
     }
     return b;
 }

@@ -1,9 +1,11 @@
 // ocd_jobs.hip -- uneven detection jobs in one persistent launch.
 //
 // Every job is cut into tiles of consecutive (subcarrier, symbol) vectors.  A
-// tile runs exactly the one-problem code (forward_tile) with NPL = 16 complex
-// entries per lane, so a job with B antennas uses L = 4, 8, 16 or 32 lanes per
-// vector (B <= 16 L): one register footprint serves every job.  Tiles are sorted
+// tile runs exactly the one-problem code (forward_tile) with NPL = 8 complex
+// entries per lane, so a job with B antennas uses L = B/8 lanes per vector
+// (4, 8, 16 or 32): one register footprint serves every job, and a tile of
+// whole subcarriers fills most of a 512-lane workgroup whatever B is, while its
+// H_w slots stay within one LDS budget (two tiles per CU).  Tiles are sorted
 // longest-first (LPT) and persistent workgroups pop them from a device counter
 // until the queue is empty.  The queue reset and the persistent kernel can be
 // captured once into a hipGraph and replayed; the job and tile tables live in
@@ -15,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -24,8 +27,8 @@
 
 namespace ocd {
 
-constexpr int JOB_NPL = 16;
-constexpr int JOB_THREADS = 256;
+constexpr int JOB_NPL = 8;
+constexpr int JOB_THREADS = 512;
 
 struct JobDesc {
     Params P;
@@ -42,32 +45,53 @@ struct TileDesc {
 
 constexpr size_t HEADER_BYTES = 256;
 
+// Two schedules over the same LPT-ordered tile table, in one launch:
+//   persistent = 0: one workgroup per tile (grid = number of tiles, tile =
+//                   blockIdx.x); the hardware dispatcher starts workgroups as
+//                   others retire, so one tile's loads overlap another's work.
+//   persistent = 1: a fixed grid; each workgroup claims its next tile from the
+//                   queue head while it works on the current one.  Every
+//                   workgroup stops when the queue is exhausted.
 template <bool F16, bool BOX>
-__global__ __launch_bounds__(JOB_THREADS) void k_jobs(const JobDesc *jobs, const TileDesc *tiles,
-                                                      unsigned int *next, int ntiles)
+__global__ __launch_bounds__(JOB_THREADS, 4) void k_jobs(const JobDesc *__restrict__ jobs,
+                                                      const TileDesc *__restrict__ tiles,
+                                                      unsigned int *__restrict__ next, int ntiles,
+                                                      int persistent)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_tile;
-    for (;;) {
-        __syncthreads();   // the previous tile is done with LDS and s_tile
+    int ti = blockIdx.x;
+    if (persistent) {
         if (threadIdx.x == 0) s_tile = (int)atomicAdd(next, 1u);
         __syncthreads();
-        const int ti = __builtin_amdgcn_readfirstlane(s_tile);
-        if (ti >= ntiles) break;
+        ti = __builtin_amdgcn_readfirstlane(s_tile);
+    }
+    while (ti < ntiles) {
+        // claim the following tile now; its value is published after this tile
+        int claimed = ntiles;
+        if (persistent && threadIdx.x == 0) claimed = (int)atomicAdd(next, 1u);
+        // the tile and its job are the same for the whole workgroup: keep them in
+        // scalar registers (the descriptor is then read with scalar loads)
         const TileDesc td = tiles[ti];
-        const JobDesc &jd = jobs[td.job];
+        const int job = __builtin_amdgcn_readfirstlane(td.job);
+        const JobDesc &jd = jobs[job];
         const Params P = jd.P;
         Tile t;
-        t.vbase = td.vbase;
-        t.nvb = td.nvb;
-        t.w_first = td.vbase / P.S;
-        t.nslots = (td.vbase + td.nvb - 1) / P.S - t.w_first + 1;
+        t.vbase = __builtin_amdgcn_readfirstlane(td.vbase);
+        t.nvb = __builtin_amdgcn_readfirstlane(td.nvb);
+        t.w_first = t.vbase / P.S;
+        t.nslots = (t.vbase + t.nvb - 1) / P.S - t.w_first + 1;
         switch (jd.L) {
         case 4: forward_tile<4, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 4, false), t); break;
         case 8: forward_tile<8, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 8, false), t); break;
         case 16: forward_tile<16, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 16, false), t); break;
         default: forward_tile<32, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 32, false), t); break;
         }
+        if (!persistent) break;
+        __syncthreads();   // this tile is done with LDS (and with s_tile)
+        if (threadIdx.x == 0) s_tile = claimed;
+        __syncthreads();
+        ti = __builtin_amdgcn_readfirstlane(s_tile);
     }
 }
 
@@ -77,13 +101,19 @@ __global__ void k_reset_queue(unsigned int *next) { *next = 0u; }
 
 struct JobsPlan {
     std::vector<JobDesc> jobs;
-    std::vector<TileDesc> tiles;
+    // LPT-ordered tiles; shared and cached per (job shapes, policy), since building
+    // and sorting them costs far more host time than a launch
+    std::shared_ptr<const std::vector<TileDesc>> tiles;
     size_t lds_max = 0;
     bool f16 = false, box = false;
 };
 
+static std::mutex g_tiles_mu;
+static std::map<std::string, std::shared_ptr<const std::vector<TileDesc>>> g_tiles;
+static std::string jobs_hash(const ocd_problem *jobs, int n);
+
 // Tile-size policies the batch tuner chooses from:
-//   0  every lane group of the workgroup busy (tiles of 256/L vectors)
+//   0  every lane group of the workgroup busy (tiles of 512/L vectors)
 //   1  tiles of whole subcarriers (a multiple of S vectors), else policy 0
 //   2  half-size tiles (more tiles, better balance, less LDS per tile)
 constexpr int N_POLICIES = 3;
@@ -108,24 +138,25 @@ static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, JobsPlan
         if (st != OCD_OK) return st;
         if ((pb->storage == OCD_STORE_F16) != out.f16) return OCD_EINVAL;
         if ((pb->mode != OCD_MMSE) != out.box) return OCD_EINVAL;
-        if (pb->B > 16 * 32) return OCD_EUNSUPPORTED;
+        if (pb->B > JOB_NPL * 32) return OCD_EUNSUPPORTED;
         int L = 4;
-        while (16 * L < pb->B) L *= 2;
+        while (JOB_NPL * L < pb->B) L *= 2;
         ocd_plan pl = {L, tile_vectors(policy, L, pb->S), 0, 0};
         Params P;
         int npl, threads;
         size_t lds;
         bool ok = false;
+        // keep two tiles per CU: at most half of the LDS (whole subcarriers first)
+        const size_t budget = (size_t)lds_limit_bytes() / 2 - 64;
         while (pl.vectors_per_block >= 1) {
-            if (make_params(pb, pl, nullptr, false, P, npl, threads, lds) && npl == JOB_NPL) {
-                // carve() sizes the per-vector z rows for every lane group
+            if (make_params(pb, pl, nullptr, false, P, npl, threads, lds) && npl == JOB_NPL &&
+                lds_bytes(P, JOB_THREADS / L, false) <= budget) {
                 lds = lds_bytes(P, JOB_THREADS / L, false);
-                if (lds <= (size_t)lds_limit_bytes()) {
-                    ok = true;
-                    break;
-                }
+                ok = true;
+                break;
             }
-            pl.vectors_per_block /= 2;
+            const int v = pl.vectors_per_block;
+            pl.vectors_per_block = (v > pb->S && v % pb->S == 0) ? v - pb->S : v / 2;
         }
         if (!ok) return OCD_EUNSUPPORTED;
         JobDesc jd;
@@ -134,29 +165,46 @@ static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, JobsPlan
         jd.L = L;
         out.jobs.push_back(jd);
         out.lds_max = std::max(out.lds_max, lds);
-        const long nvec = (long)pb->W * pb->S;
+    }
+    char pk[16];
+    std::snprintf(pk, sizeof pk, "|p%d", policy);
+    const std::string key = jobs_hash(jobs, n) + pk;
+    std::lock_guard<std::mutex> lk(g_tiles_mu);
+    auto it = g_tiles.find(key);
+    if (it != g_tiles.end()) {
+        out.tiles = it->second;
+        return OCD_OK;
+    }
+    auto tiles = std::make_shared<std::vector<TileDesc>>();
+    for (int j = 0; j < n; ++j) {
+        const Params &P = out.jobs[j].P;
+        const long nvec = (long)P.W * P.S;
         for (long v = 0; v < nvec; v += P.vpb) {
             TileDesc td;
             td.vbase = (int)v;
             td.job = j;
             td.nvb = (int)std::min<long>(P.vpb, nvec - v);
             td.pad_ = 0;
-            out.tiles.push_back(td);
+            tiles->push_back(td);
         }
     }
     // longest processing time first: cost ~ vectors x sweeps x users x padded antennas
-    auto cost = [&](const TileDesc &t) {
-        const Params &P = out.jobs[t.job].P;
-        return (double)t.nvb * P.K * P.U * P.Bpad + 4.0 * P.U * P.Bpad;
-    };
-    std::stable_sort(out.tiles.begin(), out.tiles.end(),
-                     [&](const TileDesc &a, const TileDesc &b) { return cost(a) > cost(b); });
+    std::vector<double> jcost(n);
+    for (int j = 0; j < n; ++j) {
+        const Params &P = out.jobs[j].P;
+        jcost[j] = (double)P.K * P.U * P.Bpad;
+    }
+    std::stable_sort(tiles->begin(), tiles->end(), [&](const TileDesc &a, const TileDesc &b) {
+        return a.nvb * jcost[a.job] > b.nvb * jcost[b.job];
+    });
+    out.tiles = tiles;
+    g_tiles[key] = tiles;
     return OCD_OK;
 }
 
 static size_t table_bytes(const JobsPlan &jp)
 {
-    return jp.jobs.size() * sizeof(JobDesc) + jp.tiles.size() * sizeof(TileDesc);
+    return jp.jobs.size() * sizeof(JobDesc) + jp.tiles->size() * sizeof(TileDesc);
 }
 
 // ------------------------------------------------------------------ launch state
@@ -165,6 +213,8 @@ struct Staging {
     void *pinned = nullptr;
     size_t bytes = 0;
     hipEvent_t uploaded = nullptr;
+    std::vector<unsigned char> last_jobs;           // job table last uploaded here
+    std::shared_ptr<const std::vector<TileDesc>> last_tiles;   // tile table last uploaded here
 };
 
 struct GraphEntry {
@@ -175,20 +225,49 @@ struct GraphEntry {
 static std::mutex g_mu;
 static std::map<void *, Staging> g_staging;
 static std::map<std::string, GraphEntry> g_graphs;
-static std::map<std::string, int> g_policy;
+static std::map<std::string, int> g_choice;
 static hipStream_t g_capture_stream = nullptr;
 
-static int persistent_grid(const JobsPlan &jp, const void *fn)
+// A schedule choice: persistent (1) or one workgroup per tile (0), times a tile policy.
+constexpr int N_CHOICES = 2 * N_POLICIES;
+constexpr int DEFAULT_CHOICE = 1;   // one workgroup per tile, whole-subcarrier tiles
+static int choice_persistent(int c) { return c / N_POLICIES; }
+static int choice_policy(int c) { return c % N_POLICIES; }
+
+// Persistent grid: as many workgroups as fit on the device at once (LDS and the
+// 4-waves-per-SIMD register budget of k_jobs), never more than there are tiles.
+static int persistent_grid(const JobsPlan &jp)
 {
-    int dev = 0, ncu = 256, per_cu = 1;
+    int dev = 0, ncu = 256;
+    size_t lds_cu = 160 * 1024;
     hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
         ncu = prop.multiProcessorCount;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, JOB_THREADS, jp.lds_max) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    const long want = (long)ncu * per_cu;
-    return (int)std::max<long>(1, std::min<long>(want, (long)jp.tiles.size()));
+        if (prop.maxSharedMemoryPerMultiProcessor > 0) lds_cu = prop.maxSharedMemoryPerMultiProcessor;
+    }
+    const int by_waves = (4 * 4 * 64) / JOB_THREADS;   // 4 waves per SIMD, 4 SIMDs per CU
+    const int by_lds = (int)(lds_cu / std::max<size_t>(jp.lds_max, 1));
+    const int per_cu = std::max(1, std::min(by_waves, by_lds));
+    return (int)std::max<long>(1, std::min<long>((long)ncu * per_cu, (long)jp.tiles->size()));
+}
+
+static hipError_t enqueue_jobs(const JobsPlan &jp, unsigned char *ws, int persistent, hipStream_t s)
+{
+    unsigned int *next = reinterpret_cast<unsigned int *>(ws);
+    const JobDesc *jobs = reinterpret_cast<const JobDesc *>(ws + HEADER_BYTES);
+    const TileDesc *tiles = reinterpret_cast<const TileDesc *>(ws + HEADER_BYTES +
+                                                               jp.jobs.size() * sizeof(JobDesc));
+    const int ntiles = (int)jp.tiles->size();
+    const int grid = persistent ? persistent_grid(jp) : ntiles;
+    if (persistent) hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, next);
+    if (jp.f16) {
+        if (jp.box) hipLaunchKernelGGL((k_jobs<true, true>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles, persistent);
+        else hipLaunchKernelGGL((k_jobs<true, false>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles, persistent);
+    } else {
+        if (jp.box) hipLaunchKernelGGL((k_jobs<false, true>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles, persistent);
+        else hipLaunchKernelGGL((k_jobs<false, false>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles, persistent);
+    }
+    return hipGetLastError();
 }
 
 static const void *jobs_kernel(bool f16, bool box)
@@ -199,29 +278,16 @@ static const void *jobs_kernel(bool f16, bool box)
                : reinterpret_cast<const void *>(k_jobs<false, false>);
 }
 
-static hipError_t enqueue_jobs(const JobsPlan &jp, unsigned char *ws, int grid, hipStream_t s)
-{
-    unsigned int *next = reinterpret_cast<unsigned int *>(ws);
-    const JobDesc *jobs = reinterpret_cast<const JobDesc *>(ws + HEADER_BYTES);
-    const TileDesc *tiles = reinterpret_cast<const TileDesc *>(ws + HEADER_BYTES +
-                                                               jp.jobs.size() * sizeof(JobDesc));
-    const int ntiles = (int)jp.tiles.size();
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, next);
-    if (jp.f16) {
-        if (jp.box) hipLaunchKernelGGL((k_jobs<true, true>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles);
-        else hipLaunchKernelGGL((k_jobs<true, false>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles);
-    } else {
-        if (jp.box) hipLaunchKernelGGL((k_jobs<false, true>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles);
-        else hipLaunchKernelGGL((k_jobs<false, false>), dim3(grid), dim3(JOB_THREADS), jp.lds_max, s, jobs, tiles, next, ntiles);
-    }
-    return hipGetLastError();
-}
-
-// Uploads the tables through the library's pinned buffer for this workspace.
+// Uploads the tables through the library's pinned buffer for this workspace,
+// unless the workspace already holds exactly these bytes.
 static hipError_t upload_tables(const JobsPlan &jp, unsigned char *ws, hipStream_t s)
 {
-    const size_t bytes = table_bytes(jp);
+    const size_t nj = jp.jobs.size() * sizeof(JobDesc), nt = jp.tiles->size() * sizeof(TileDesc);
+    const size_t bytes = nj + nt;
     Staging &st = g_staging[ws];
+    if (st.last_tiles == jp.tiles && st.last_jobs.size() == nj &&
+        std::memcmp(st.last_jobs.data(), jp.jobs.data(), nj) == 0)
+        return hipSuccess;
     hipError_t e = hipSuccess;
     if (st.uploaded) {
         e = hipEventSynchronize(st.uploaded);   // the last copy from this buffer is done
@@ -239,11 +305,12 @@ static hipError_t upload_tables(const JobsPlan &jp, unsigned char *ws, hipStream
         st.bytes = bytes;
     }
     unsigned char *h = static_cast<unsigned char *>(st.pinned);
-    std::memcpy(h, jp.jobs.data(), jp.jobs.size() * sizeof(JobDesc));
-    std::memcpy(h + jp.jobs.size() * sizeof(JobDesc), jp.tiles.data(),
-                jp.tiles.size() * sizeof(TileDesc));
+    std::memcpy(h, jp.jobs.data(), nj);
+    std::memcpy(h + nj, jp.tiles->data(), nt);
     e = hipMemcpyAsync(ws + HEADER_BYTES, h, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
+    st.last_jobs.assign(h, h + nj);
+    st.last_tiles = jp.tiles;
     return hipEventRecord(st.uploaded, s);
 }
 
@@ -279,27 +346,27 @@ static std::string jobs_hash(const ocd_problem *jobs, int n)
     return buf;
 }
 
-static ocd_status run_policy(const ocd_problem *jobs, int n, int policy, const void *const *H,
+static ocd_status run_choice(const ocd_problem *jobs, int n, int choice, const void *const *H,
                              const void *const *y, float *const *z, float *const *llr,
                              unsigned char *ws, size_t ws_bytes, bool use_graph, hipStream_t s)
 {
     JobsPlan jp;
-    ocd_status st = plan_jobs(jobs, n, policy, jp);
+    ocd_status st = plan_jobs(jobs, n, choice_policy(choice), jp);
     if (st != OCD_OK) return st;
     if (HEADER_BYTES + table_bytes(jp) > ws_bytes) return OCD_EINVAL;
-    if (jp.tiles.empty()) return OCD_OK;
+    if (jp.tiles->empty()) return OCD_OK;
     fill_pointers(jp, H, y, z, llr);
     const void *fn = jobs_kernel(jp.f16, jp.box);
     if (jp.lds_max > 65536 &&
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)jp.lds_max) != hipSuccess)
         return OCD_EDEVICE;
-    const int grid = persistent_grid(jp, fn);
+    const int persistent = choice_persistent(choice);
     if (upload_tables(jp, ws, s) != hipSuccess) return OCD_EDEVICE;
-    if (!use_graph) return enqueue_jobs(jp, ws, grid, s) == hipSuccess ? OCD_OK : OCD_EDEVICE;
+    if (!use_graph) return enqueue_jobs(jp, ws, persistent, s) == hipSuccess ? OCD_OK : OCD_EDEVICE;
 
     char key[256];
     std::snprintf(key, sizeof key, "%p|%zu|%zu|%zu|%d|%d|%d", (void *)ws, jp.jobs.size(),
-                  jp.tiles.size(), jp.lds_max, grid, (int)jp.f16, (int)jp.box);
+                  jp.tiles->size(), jp.lds_max, choice, (int)jp.f16, (int)jp.box);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
         if (!g_capture_stream &&
@@ -308,7 +375,7 @@ static ocd_status run_policy(const ocd_problem *jobs, int n, int policy, const v
         GraphEntry ge;
         if (hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return OCD_EDEVICE;
-        hipError_t e = enqueue_jobs(jp, ws, grid, g_capture_stream);
+        hipError_t e = enqueue_jobs(jp, ws, persistent, g_capture_stream);
         hipError_t e2 = hipStreamEndCapture(g_capture_stream, &ge.graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (ge.graph) (void)hipGraphDestroy(ge.graph);
@@ -353,34 +420,35 @@ extern "C" ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const
     std::lock_guard<std::mutex> lk(g_mu);
     unsigned char *ws = static_cast<unsigned char *>(workspace);
     const std::string hk = jobs_hash(jobs, n_jobs);
-    int policy = 1;
-    auto pit = g_policy.find(hk);
-    if (pit != g_policy.end()) policy = pit->second;
+    int choice = DEFAULT_CHOICE;
+    auto pit = g_choice.find(hk);
+    if (pit != g_choice.end()) choice = pit->second;
     if (flags & OCD_JOBS_TUNE) {
-        // batch tuner: time every tile policy on the caller's buffers
+        // batch tuner: time every (schedule, tile policy) on the caller's buffers
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return OCD_EDEVICE;
         if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OCD_EDEVICE; }
         float best_ms = 1e30f;
-        int best = policy;
-        for (int pol = 0; pol < N_POLICIES; ++pol) {
-            ocd_status st = run_policy(jobs, n_jobs, pol, H, y, z, llr, ws, workspace_bytes, false, stream);
+        int best = choice;
+        for (int c = 0; c < N_CHOICES; ++c) {
+            ocd_status st = run_choice(jobs, n_jobs, c, H, y, z, llr, ws, workspace_bytes, false, stream);
             if (st != OCD_OK) continue;
             (void)hipEventRecord(e0, stream);
             for (int rep = 0; rep < 3 && st == OCD_OK; ++rep)
-                st = run_policy(jobs, n_jobs, pol, H, y, z, llr, ws, workspace_bytes, false, stream);
+                st = run_choice(jobs, n_jobs, c, H, y, z, llr, ws, workspace_bytes, false, stream);
             (void)hipEventRecord(e1, stream);
             if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) continue;
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) { best_ms = ms; best = pol; }
+            if (ms < best_ms) { best_ms = ms; best = c; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        policy = best;
-        g_policy[hk] = policy;
+        choice = best;
+        g_choice[hk] = choice;
     }
-    return run_policy(jobs, n_jobs, policy, H, y, z, llr, ws, workspace_bytes,
+    if (flags & OCD_JOBS_PERSISTENT) choice = N_POLICIES + choice_policy(choice);
+    return run_choice(jobs, n_jobs, choice, H, y, z, llr, ws, workspace_bytes,
                       (flags & OCD_JOBS_GRAPH) != 0, stream);
 }
 
@@ -400,4 +468,6 @@ extern "C" void ocd_release_graphs(void)
         if (kv.second.pinned) (void)hipHostFree(kv.second.pinned);
     }
     g_staging.clear();
+    std::lock_guard<std::mutex> lt(g_tiles_mu);
+    g_tiles.clear();
 }

@@ -11,11 +11,14 @@ struct Smem {
     float2 *H;     // [maxslots][slot_stride]: H_w columns, FP32, zero-padded to Bpad
     float *g;      // [maxslots][U]: ||h_u||^2
     float2 *dp;    // [maxslots][Kt][U]: (d_u^-1, p_u)
-    float2 *z;     // [vpb_cap][U]: current z of each vector
-    float2 *zprev; // [vpb_cap][U]: adjoint only, z^(k-1) of the sweep being reversed
-    float2 *zbar;  // [vpb_cap][U]: adjoint only, dLoss/dz
-    float *part;   // [vpb_cap][2]: adjoint only, per-group partial sums
+    float2 *z;     // [vpb + 1][U]: current z of each vector; idle groups share the last row
+    float2 *zprev; // [vpb + 1][U]: adjoint only, z^(k-1) of the sweep being reversed
+    float2 *zbar;  // [vpb + 1][U]: adjoint only, dLoss/dz
+    float *part;   // [vpb_cap]: adjoint only, per-group partial sums
 };
+
+// Row of the per-vector LDS arrays used by lane group grp.
+__device__ __forceinline__ int zrow_of(const Params &P, int grp) { return grp < P.vpb ? grp : P.vpb; }
 
 __device__ __forceinline__ Smem carve(unsigned char *smem, const Params &P, int vpb_cap,
                                       bool backward)
@@ -30,17 +33,19 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const Params &P, int 
     off = (off + 7) & ~(size_t)7;
     s.dp = reinterpret_cast<float2 *>(smem + off);
     off += (size_t)P.maxslots * Kt * P.U * 8;
+    const size_t zrows = (size_t)(P.vpb + 1) * P.U * 8;
     s.z = reinterpret_cast<float2 *>(smem + off);
-    off += (size_t)vpb_cap * P.U * 8;
+    off += zrows;
     s.zprev = s.zbar = nullptr;
     s.part = nullptr;
     if (backward) {
         s.zprev = reinterpret_cast<float2 *>(smem + off);
-        off += (size_t)vpb_cap * P.U * 8;
+        off += zrows;
         s.zbar = reinterpret_cast<float2 *>(smem + off);
-        off += (size_t)vpb_cap * P.U * 8;
+        off += zrows;
         s.part = reinterpret_cast<float *>(smem + off);
     }
+    (void)vpb_cap;
     return s;
 }
 

@@ -54,7 +54,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
 
     const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
     const float2 *dps = sm.dp + (size_t)slot * Kt * U;
-    float2 *zv = sm.z + (size_t)grp * U;
+    float2 *zv = sm.z + (size_t)zrow_of(P, grp) * U;
     for (int u = 0; u < U; ++u) zv[u] = make_float2(0.f, 0.f);   // z^(0) = 0
 
     // K sweeps over the users in order (Alg. 1); with several waves per SIMD

@@ -48,8 +48,9 @@ def _make(ocd, storage="f32", jobs=JOBS, S=14, Q=6):
 
 
 def _lanes(B):
+    # the batched kernel gives each vector B/8 lanes (8 complex entries per lane)
     L = 4
-    while 16 * L < B:
+    while 8 * L < B:
         L *= 2
     return L
 
@@ -63,21 +64,33 @@ def test_jobs_match_oracle_and_single_launches(ocd):
         zo, Lo, _ = oracle_ref(wl["H"], wl["y"], pb.K, pb.Q, "mmse", pb.N0)
         assert z_rel_err(host(z[j]), zo) <= Z_TOL_F32, j
         assert llr_rel_err(host(L[j]), Lo) <= LLR_TOL_F32, j
-        # same lane split and 16 entries per lane as the batched kernel: same bits
+        # same lane split and entries per lane as the batched kernel: same bits
         ocd.ocd_set_plan(pb, ocd.Plan(_lanes(pb.B), 14, 0, 0))
         z1, L1, _ = ocd.detect(Hs[j], ys[j], pb.K, pb.Q, "mmse", pb.N0)
         torch.cuda.synchronize()
         assert torch.equal(z1, z[j]) and torch.equal(L1, L[j]), j
 
 
-def test_jobs_graph_replays_match_eager(ocd):
+def test_jobs_persistent_schedule_matches(ocd):
+    """The persistent schedule (workgroups popping tiles from the device queue)
+    computes the same bits as one workgroup per tile."""
+    probs, Hs, ys, wls = _make(ocd)
+    z0, L0, ws = ocd.detect_jobs(probs, Hs, ys)
+    z1, L1, _ = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_PERSISTENT, workspace=ws)
+    torch.cuda.synchronize()
+    for j in range(len(probs)):
+        assert torch.equal(z1[j], z0[j]) and torch.equal(L1[j], L0[j]), j
+
+
+@pytest.mark.parametrize("extra", [0, 4])
+def test_jobs_graph_replays_match_eager(ocd, extra):
     probs, Hs, ys, wls = _make(ocd)
     z0, L0, ws = ocd.detect_jobs(probs, Hs, ys)
     torch.cuda.synchronize()
     for rep in range(3):
         z = [torch.full_like(t, float("nan")) for t in z0]
         L = [torch.full_like(t, float("nan")) for t in L0]
-        ocd.ocd_detect_jobs(probs, Hs, ys, z, L, ws, flags=ocd.OCD_JOBS_GRAPH)
+        ocd.ocd_detect_jobs(probs, Hs, ys, z, L, ws, flags=ocd.OCD_JOBS_GRAPH | extra)
         torch.cuda.synchronize()
         # eager work and a synchronisation between replays
         _ = ocd.detect(Hs[1], ys[1], probs[1].K, probs[1].Q, "mmse", probs[1].N0)
