@@ -133,6 +133,10 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
     P.Es = pb->Es; P.N0 = pb->N0;
     P.beta = pb->beta > 0.f ? pb->beta : box_edge(pb->Q) * std::sqrt(pb->Es);
     P.lam_default = pb->mode == OCD_BOX ? 0.f : pb->N0 / pb->Es;
+    P.sqEs = std::sqrt(pb->Es);
+    P.qscale = qam_scale(pb->Q);
+    P.invU = 1.0f / (float)pb->U;
+    P.invS = 1.0 / (double)pb->S;
     P.lambda = lambda;
     const long nvec = (long)pb->W * pb->S;
     P.nblocks = (int)((nvec + P.vpb - 1) / P.vpb);

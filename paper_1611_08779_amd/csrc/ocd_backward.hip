@@ -60,14 +60,14 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     const int grp = threadIdx.x / L, j = threadIdx.x % L;
     const bool active = grp < t.nvb;
     const int v = t.vbase + (active ? grp : 0);
-    const int slot = v / P.S - t.w_first;
+    const int slot = slot_of_group(P, t, active ? grp : 0);
 
     // H_w chunk loads, then y, then the LDS stores of H (see forward_tile)
     const int chunks = t.nslots * U * (Bpad >> 1);
     float4 hbuf[STAGE_CHUNKS];
     stage_h_load<F16>(P, t.w_first, chunks, 0, hbuf);
     float2 r[NPL];
-    load_vector<L, NPL, F16>(P, P.y, v, j, active, r);
+    load_vector<L, NPL, F16>(P, P.y, t, grp, j, active, r);
     stage_h_store(P, sm, chunks, 0, hbuf);
     stage_h_copy<F16>(P, sm, t.w_first, chunks, STAGE_CHUNKS * (int)blockDim.x);
     stage_preprocess(P, sm, t.w_first, t.nslots);
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     // soft-output adjoint, one owner lane per user
     const float lamK = P.lambda ? P.lambda[K - 1] : P.lam_default;
     const float2 *dpK = dps + (P.per_sweep ? K - 1 : 0) * U;
-    const float sqEs = sqrtf(P.Es), scale = qam_scale(P.Q);
+    const float sqEs = P.sqEs, scale = P.qscale;
     float lamK_bar = 0.f;
     for (int u = j; u < U; u += L) {
         float2 zbar = make_float2(0.f, 0.f);

@@ -95,6 +95,25 @@ __device__ __forceinline__ float4 load_pair(const void *base, long e)
     }
 }
 
+// Bytes per complex entry in storage.
+template <bool F16>
+__device__ __forceinline__ constexpr unsigned cbytes() { return F16 ? 4u : 8u; }
+
+// Two consecutive complex entries at byte offset `off` from a workgroup-uniform
+// base: the address is a scalar base plus a 32-bit lane offset.
+template <bool F16>
+__device__ __forceinline__ float4 load_pair_at(const unsigned char *base, unsigned off)
+{
+    if constexpr (!F16) {
+        const f32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(base + off));
+        return make_float4(q.x, q.y, q.z, q.w);
+    } else {
+        const u32x2_t q = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t *>(base + off));
+        const float2 a = half2_to_float2(q.x), b = half2_to_float2(q.y);
+        return make_float4(a.x, a.y, b.x, b.y);
+    }
+}
+
 // Load `N` consecutive complex entries starting at element `e` of a row,
 // converting to FP32; entries at or beyond `limit` read as zero.  General
 // (branchy) path, used where vector loads are not allowed.
@@ -163,6 +182,46 @@ __device__ __forceinline__ void axis_llr(float xc, float scale, float rho, float
             else d0 = fminf(d0, d[m]);
         }
         out[bb] = rho * (d0 - d1);
+    }
+}
+
+// The same metrics in closed form, t = xc / scale (levels at the odd integers
+// of [-(M-1), M-1]), D_b = min over bit b = 0 of (t - A)^2 - min over bit b = 1.
+//
+// MSB: the label bit is 1 exactly for the positive levels.  For t >= 0 the
+// nearest negative level is -1 and the nearest positive one is the odd integer
+// n nearest to t clamped to [1, M-1], so D = (t+1)^2 - (t-n)^2 = (n+1)(2t+1-n);
+// D is odd in t.  Every further bit of the reflected Gray label takes the same
+// value on A and -A, so its two minima depend on |t| only; about the centre M/2
+// of the positive half its levels form an M/2-PAM whose labels are those of an
+// M/2-PAM with the MSB inverted.  Hence D_1 = -msb_{M/2}(|t| - M/2) and each
+// further bit folds once more.
+template <int M>
+__device__ __forceinline__ float pam_msb_metric(float t)
+{
+    const float u = fabsf(t);
+    float e;
+    if constexpr (M == 2) {
+        e = 4.0f * u;
+    } else {
+        const float n = fminf(fmaxf(fmaf(2.0f, floorf(0.5f * u), 1.0f), 1.0f), (float)(M - 1));
+        e = (n + 1.0f) * fmaf(2.0f, u, 1.0f - n);
+    }
+    return copysignf(e, t);
+}
+
+template <int HALF>
+__device__ __forceinline__ void pam_metrics(float t, float *D)
+{
+    constexpr int M = 1 << HALF;
+    D[0] = pam_msb_metric<M>(t);
+    if constexpr (HALF >= 2) {
+        const float w1 = fabsf(t) - (float)(M / 2);
+        D[1] = -pam_msb_metric<M / 2>(w1);
+        if constexpr (HALF >= 3) {
+            const float w2 = fabsf(w1) - (float)(M / 4);
+            D[2] = -pam_msb_metric<M / 4>(w2);
+        }
     }
 }
 

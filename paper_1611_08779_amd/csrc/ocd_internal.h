@@ -21,6 +21,10 @@ struct Params {
     int nblocks;
     float Es, N0, beta;
     float lam_default;   // regulariser when lambda == nullptr
+    float sqEs;          // sqrt(Es)
+    float qscale;        // level spacing of the unit-energy square QAM
+    float invU;          // 1 / U (slot of a staged H row without an integer divide)
+    double invS;         // 1 / S (slot of a vector without an integer divide)
     const float *lambda; // device [K] or nullptr
     const void *H;       // [W][U][B] complex (FP32 or FP16 pairs)
     const void *y;       // [W][S][B]
@@ -46,6 +50,7 @@ inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward)
     b += (size_t)p.maxslots * p.U * 4;               // g
     b = (b + 7) & ~(size_t)7;
     b += (size_t)p.maxslots * Kt * p.U * 8;          // (dinv, p) pairs
+    b += (size_t)p.maxslots * p.U * 8;               // soft-output coefficients
     b += (size_t)(p.vpb + 1) * p.U * 8;              // z per vector (+ idle groups' row)
     if (backward) {
         b += (size_t)(p.vpb + 1) * p.U * 8;          // z^(k-1) row per vector

@@ -11,6 +11,7 @@ struct Smem {
     float2 *H;     // [maxslots][slot_stride]: H_w columns, FP32, zero-padded to Bpad
     float *g;      // [maxslots][U]: ||h_u||^2
     float2 *dp;    // [maxslots][Kt][U]: (d_u^-1, p_u)
+    float2 *lc;    // [maxslots][U]: soft-output coefficients (see llr_coef)
     float2 *z;     // [vpb + 1][U]: current z of each vector; idle groups share the last row
     float2 *zprev; // [vpb + 1][U]: adjoint only, z^(k-1) of the sweep being reversed
     float2 *zbar;  // [vpb + 1][U]: adjoint only, dLoss/dz
@@ -33,6 +34,8 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const Params &P, int 
     off = (off + 7) & ~(size_t)7;
     s.dp = reinterpret_cast<float2 *>(smem + off);
     off += (size_t)P.maxslots * Kt * P.U * 8;
+    s.lc = reinterpret_cast<float2 *>(smem + off);
+    off += (size_t)P.maxslots * P.U * 8;
     const size_t zrows = (size_t)(P.vpb + 1) * P.U * 8;
     s.z = reinterpret_cast<float2 *>(smem + off);
     off += zrows;
@@ -56,6 +59,15 @@ struct Tile {
     int vbase;
     int nvb, w_first, nslots;
 };
+
+// Staged slot of lane group grp's vector: (vbase + grp) / S - w_first, from the
+// offset of the group in its first subcarrier (below 2^30): in double precision
+// (x + 1/2) / S is within 1/(2S) of an integer plus one half, so truncation is exact.
+__device__ __forceinline__ int slot_of_group(const Params &P, const Tile &tile, int grp)
+{
+    const int x = tile.vbase - tile.w_first * P.S + grp;
+    return (int)fma((double)x, P.invS, 0.5 * P.invS);
+}
 
 __device__ __forceinline__ Tile tile_of(const Params &P, int bid)
 {
@@ -87,13 +99,16 @@ __device__ __forceinline__ void stage_h_load(const Params &P, int w_first, int t
     if (P.vec_ok) {
         // B even: a chunk is wholly inside or wholly outside the row.  Out-of-range
         // chunks load a valid address and are replaced by zeros, so no load sits
-        // behind a branch and all of them are in flight together.
+        // behind a branch and all of them are in flight together.  The rows of the
+        // tile start at a workgroup-uniform address; per-lane offsets are 32-bit.
+        const unsigned char *hb =
+            static_cast<const unsigned char *>(P.H) + (size_t)rbase * P.B * cbytes<F16>();
 #pragma unroll
         for (int i = 0; i < STAGE_CHUNKS; ++i) {
             const int c = c0 + i * (int)blockDim.x + (int)threadIdx.x;
             const int row = c >> sh, b = (c & (half - 1)) << 1;
             const bool ok = c < total && b < P.B;
-            buf[i] = load_pair<F16>(P.H, ok ? (rbase + row) * P.B + b : 0);
+            buf[i] = load_pair_at<F16>(hb, ok ? (unsigned)(row * P.B + b) * cbytes<F16>() : 0u);
         }
         return;
     }
@@ -109,6 +124,13 @@ __device__ __forceinline__ void stage_h_load(const Params &P, int w_first, int t
     }
 }
 
+// row / U for the row index of a staged H_w row (row < 2^16, U <= 32): the float
+// product is within 0.5 / U of an integer plus one half, so truncation is exact.
+__device__ __forceinline__ int slot_of_row(const Params &P, int row)
+{
+    return (int)fmaf((float)row, P.invU, 0.5f * P.invU);
+}
+
 __device__ __forceinline__ void stage_h_store(const Params &P, const Smem &sm, int total, int c0,
                                               const float4 (&buf)[STAGE_CHUNKS])
 {
@@ -120,7 +142,7 @@ __device__ __forceinline__ void stage_h_store(const Params &P, const Smem &sm, i
         const int c = c0 + i * (int)blockDim.x + (int)threadIdx.x;
         if (c < total) {
             const int row = c >> sh, b = (c & (half - 1)) << 1;
-            const int slot = row / P.U;
+            const int slot = slot_of_row(P, row);
             // antennas past B (loaded from a placeholder address) become zero padding
             const float4 q = b < P.B ? buf[i] : make_float4(0.f, 0.f, 0.f, 0.f);
             *reinterpret_cast<float4 *>(sm.H + (size_t)row * P.Bpad + (size_t)slot * gap + b) = q;
@@ -140,6 +162,35 @@ __device__ __forceinline__ void stage_h_copy(const Params &P, const Smem &sm, in
     }
 }
 
+// Section III-C: approximate channel gain mu = d^-1 g (= p of the last sweep) and
+// SINR rho = mu/(1-mu) = g/lambda_K; with lambda_K = 0 (BOX) mu = 1 and the
+// finite rho = g Es/N0 is used.
+__device__ __forceinline__ void gain_sinr(const Params &P, float lamK, float g, float pK,
+                                          float *mu, float *rho)
+{
+    if (lamK > 0.f) {
+        *mu = pK;
+        *rho = g / lamK;
+    } else {
+        *mu = 1.0f;
+        *rho = g * P.Es / P.N0;
+    }
+}
+
+// Per (subcarrier, user) constants of the soft output, so that the LLRs of a
+// vector are L_b = c D_b(t) with t = z_u a (z in units of the level spacing of
+// the unit-energy constellation, after the 1/(mu sqrt(Es)) unbiasing of
+// Section III-C) and D_b the per-axis max-log metric: a = 1/(mu sqrt(Es) scale),
+// c = rho scale^2.  A user with rho or mu not positive (zero column) gets (0, 0):
+// all of its LLRs are zero.
+__device__ __forceinline__ float2 llr_coef(const Params &P, float g, float pK, float lamK)
+{
+    float mu, rho;
+    gain_sinr(P, lamK, g, pK, &mu, &rho);
+    if (!(rho > 0.f && mu > 0.f)) return make_float2(0.f, 0.f);
+    return make_float2(1.0f / (mu * P.sqEs * P.qscale), rho * P.qscale * P.qscale);
+}
+
 // Algorithm 1's preprocessing once per staged subcarrier (or a copy of the
 // precomputed values): g_u = ||h_u||^2, d_u^-1 = (g_u + lambda_k)^-1 (0 if that
 // is 1/0), p_u = d_u^-1 g_u.  Ends with a workgroup barrier, after which the
@@ -150,9 +201,14 @@ __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, i
     const int Kt = P.per_sweep ? P.K : 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
     const int rows = nslots * U;
+    const float lamK = P.lambda ? P.lambda[P.K - 1] : P.lam_default;
     if (P.g_in) {
-        for (int i = threadIdx.x; i < rows; i += blockDim.x)
-            sm.g[i] = P.g_in[(long)w_first * U + i];
+        for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+            const int slot = slot_of_row(P, i), u = i - slot * U;
+            const float g = P.g_in[(long)w_first * U + i];
+            sm.g[i] = g;
+            sm.lc[i] = llr_coef(P, g, P.p_in[((long)(w_first + slot) * Kt + Kt - 1) * U + u], lamK);
+        }
         for (int i = threadIdx.x; i < nslots * Kt * U; i += blockDim.x) {
             const long gi = (long)w_first * Kt * U + i;
             sm.dp[i] = make_float2(P.dinv_in[gi], P.p_in[gi]);
@@ -162,12 +218,18 @@ __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, i
     }
     __syncthreads();
     for (int row = wave; row < rows; row += nwaves) {
-        const int slot = row / U, u = row - slot * U;
+        const int slot = slot_of_row(P, row), u = row - slot * U;
         const float2 *h = sm.H + (size_t)slot * P.slot_stride + (size_t)u * Bpad;
         float acc = 0.f;
         for (int b = lane; b < Bpad; b += 64) acc = fmaf(h[b].x, h[b].x, fmaf(h[b].y, h[b].y, acc));
         acc = wave_sum(acc);
-        if (lane == 0) sm.g[row] = acc;
+        if (lane == 0) {
+            sm.g[row] = acc;
+            // p of the last sweep, computed as for sm.dp below
+            const float den = acc + lamK;
+            const float di = den > 0.f ? 1.0f / den : 0.f;
+            sm.lc[row] = llr_coef(P, acc, di * acc, lamK);
+        }
         for (int kt = lane; kt < Kt; kt += 64) {
             const float lam = P.lambda ? P.lambda[kt] : P.lam_default;
             const float den = acc + lam;
@@ -191,33 +253,40 @@ __device__ void stage_subcarriers(const Params &P, const Smem &sm, int w_first, 
 // while the caller stages H; antennas past B and idle groups load a placeholder
 // address and must be cleared with clear_padding() before first use.
 template <int L, int NPL, bool F16>
-__device__ __forceinline__ void load_vector(const Params &P, const void *base, int v, int j,
-                                            bool active, float2 *r)
+__device__ __forceinline__ void load_vector(const Params &P, const void *base, const Tile &tile,
+                                            int grp, int j, bool active, float2 *r)
 {
     if (P.vec_ok) {
+        // the tile's vectors start at a workgroup-uniform address; 32-bit offsets
+        const unsigned char *tb =
+            static_cast<const unsigned char *>(base) + (size_t)tile.vbase * P.B * cbytes<F16>();
 #pragma unroll
         for (int c = 0; c < NPL / 2; ++c) {
             const int b = 2 * (j + L * c);
             const bool ok = active && b < P.B;
-            const float4 q = load_pair<F16>(base, ok ? (long)v * P.B + b : 0);
+            const float4 q =
+                load_pair_at<F16>(tb, ok ? (unsigned)(grp * P.B + b) * cbytes<F16>() : 0u);
             r[2 * c] = make_float2(q.x, q.y);
             r[2 * c + 1] = make_float2(q.z, q.w);
         }
         return;
     }
+    const long v = (long)tile.vbase + grp;
 #pragma unroll
     for (int c = 0; c < NPL / 2; ++c) {
         const int b = 2 * (j + L * c);
-        if (active) load_chunk<F16, 2>(base, (long)v * P.B + b, b, P.B, false, &r[2 * c]);
+        if (active) load_chunk<F16, 2>(base, v * P.B + b, b, P.B, false, &r[2 * c]);
         else r[2 * c] = r[2 * c + 1] = make_float2(0.f, 0.f);
     }
 }
 
-// Zeroes the entries load_vector filled from placeholder addresses.
+// Zeroes the entries load_vector filled from placeholder addresses.  With
+// B = L * NPL there is no padding, and the residuals of idle groups are never
+// stored nor mixed into another group's sums, so nothing needs clearing.
 template <int L, int NPL>
 __device__ __forceinline__ void clear_padding(const Params &P, int j, bool active, float2 *r)
 {
-    if (!P.vec_ok) return;
+    if (!P.vec_ok || P.B == P.Bpad) return;
 #pragma unroll
     for (int c = 0; c < NPL / 2; ++c) {
         const bool ok = active && 2 * (j + L * c) < P.B;
@@ -238,23 +307,39 @@ __device__ __forceinline__ void load_column(const float2 *col, int j, float2 *h)
     }
 }
 
-// conj(h)^T r over this lane's entries, two independent accumulator pairs.
+// Operands of one coordinate update: this lane's part of column u, (d_u^-1, p_u)
+// and the current z_u.
+template <int NPL>
+struct UpdateOperands {
+    float2 h[NPL];
+    float2 dp, zo;
+};
+
+template <int L, int NPL>
+__device__ __forceinline__ void fetch_operands(const float2 *Hs, int Bpad, const float2 *dpk,
+                                               const float2 *zv, int u, int j,
+                                               UpdateOperands<NPL> &o)
+{
+    load_column<L, NPL>(Hs + (size_t)u * Bpad, j, o.h);
+    o.dp = dpk[u];
+    o.zo = zv[u];
+}
+
+// conj(h)^T r over this lane's entries.  One accumulator per component: the
+// real and imaginary chains alternate, which keeps dependent FMAs two issue
+// slots apart (their latency), and there is no final merge.
 template <int NPL>
 __device__ __forceinline__ float2 partial_inner(const float2 *h, const float2 *r)
 {
-    float ar0 = 0.f, ai0 = 0.f, ar1 = 0.f, ai1 = 0.f;
+    float ar = 0.f, ai = 0.f;
 #pragma unroll
-    for (int i = 0; i < NPL; i += 2) {
-        ar0 = fmaf(h[i].x, r[i].x, ar0);
-        ar0 = fmaf(h[i].y, r[i].y, ar0);
-        ai0 = fmaf(h[i].x, r[i].y, ai0);
-        ai0 = fmaf(-h[i].y, r[i].x, ai0);
-        ar1 = fmaf(h[i + 1].x, r[i + 1].x, ar1);
-        ar1 = fmaf(h[i + 1].y, r[i + 1].y, ar1);
-        ai1 = fmaf(h[i + 1].x, r[i + 1].y, ai1);
-        ai1 = fmaf(-h[i + 1].y, r[i + 1].x, ai1);
+    for (int i = 0; i < NPL; ++i) {
+        ar = fmaf(h[i].x, r[i].x, ar);
+        ai = fmaf(h[i].x, r[i].y, ai);
+        ar = fmaf(h[i].y, r[i].y, ar);
+        ai = fmaf(-h[i].y, r[i].x, ai);
     }
-    return make_float2(ar0 + ar1, ai0 + ai1);
+    return make_float2(ar, ai);
 }
 
 // r <- r - h * delta (complex), this lane's entries.
@@ -299,23 +384,19 @@ __device__ __forceinline__ float2 coordinate_update(const float2 *h, float2 dp, 
         cr = fminf(fmaxf(cr, -beta), beta);
         ci = fminf(fmaxf(ci, -beta), beta);
     }
-    axpy_sub<NPL>(h, make_float2(cr - zo.x, ci - zo.y), r);
+    // r <- r - h Delta with Delta = z_u' - z_u, written with -Delta so that h enters
+    // only with positive sign (the inner product above already uses -Im h; a shared
+    // negated copy would cost one instruction per entry).  Same bits as axpy_sub.
+    const float ndr = zo.x - cr, ndi = zo.y - ci, di = ci - zo.y;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+        r[i].x = fmaf(h[i].x, ndr, r[i].x);
+        r[i].x = fmaf(h[i].y, di, r[i].x);
+        r[i].y = fmaf(h[i].x, ndi, r[i].y);
+        r[i].y = fmaf(h[i].y, ndr, r[i].y);
+    }
     return make_float2(cr, ci);
 }
 
-// Section III-C: approximate channel gain mu = d^-1 g (= p of the last sweep) and
-// SINR rho = mu/(1-mu) = g/lambda_K; with lambda_K = 0 (BOX) mu = 1 and the
-// finite rho = g Es/N0 is used.
-__device__ __forceinline__ void gain_sinr(const Params &P, float lamK, float g, float pK,
-                                          float *mu, float *rho)
-{
-    if (lamK > 0.f) {
-        *mu = pK;
-        *rho = g / lamK;
-    } else {
-        *mu = 1.0f;
-        *rho = g * P.Es / P.N0;
-    }
-}
 
 }  // namespace ocd

@@ -16,11 +16,15 @@
 
 namespace ocd {
 
+// Soft output of one axis of one user: t = the axis of z_u times a, c = the
+// LLR scale (llr_coef); writes the HALF LLRs of that axis, MSB first.
 template <int HALF>
-__device__ __forceinline__ void user_llr(float xr, float xi, float scale, float rho, float *out)
+__device__ __forceinline__ void axis_llrs(float t, float c, float *dst)
 {
-    axis_llr<HALF>(xr, scale, rho, out);         // in-phase bits
-    axis_llr<HALF>(xi, scale, rho, out + HALF);  // quadrature bits
+    float D[HALF];
+    pam_metrics<HALF>(t, D);
+#pragma unroll
+    for (int b = 0; b < HALF; ++b) dst[b] = c * D[b];
 }
 
 // Algorithm 1 and the soft output for the vectors of one tile.  The caller has
@@ -37,7 +41,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     const int grp = threadIdx.x / L, j = threadIdx.x % L;
     const bool active = grp < tile.nvb;
     const int v = tile.vbase + (active ? grp : 0);
-    const int slot = v / P.S - tile.w_first;
+    const int slot = slot_of_group(P, tile, active ? grp : 0);
 
     // H_w chunk loads first, then the receive vector (initialisation r = y):
     // both global round trips are in flight together, and the LDS stores of H
@@ -46,7 +50,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     float4 hbuf[STAGE_CHUNKS];
     stage_h_load<F16>(P, tile.w_first, chunks, 0, hbuf);
     float2 r[NPL];
-    load_vector<L, NPL, F16>(P, P.y, v, j, active, r);
+    load_vector<L, NPL, F16>(P, P.y, tile, grp, j, active, r);
     stage_h_store(P, sm, chunks, 0, hbuf);
     stage_h_copy<F16>(P, sm, tile.w_first, chunks, STAGE_CHUNKS * (int)blockDim.x);
     stage_preprocess(P, sm, tile.w_first, tile.nslots);
@@ -57,42 +61,69 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     float2 *zv = sm.z + (size_t)zrow_of(P, grp) * U;
     for (int u = 0; u < U; ++u) zv[u] = make_float2(0.f, 0.f);   // z^(0) = 0
 
-    // K sweeps over the users in order (Alg. 1); with several waves per SIMD
-    // the LDS latency of each update is hidden by the other waves.
+    // K sweeps over the users in order (Alg. 1).
     const float beta = P.beta;
-    for (int k = 0; k < P.K; ++k) {
-        const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
-        for (int u = 0; u < U; ++u) {
-            float2 h[NPL];
-            load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
-            const float2 dp = dpk[u];
-            const float2 zo = zv[u];
-            zv[u] = coordinate_update<L, NPL, BOX>(h, dp, zo, beta, r);
-        }
+    auto sweep_done = [&](int k) {
         if (P.z_hist && active)
             for (int u = j; u < U; u += L) P.z_hist[((long)v * P.K + k) * U + u] = zv[u];
+    };
+    if (U == 1) {
+        // a single user: every update reads the z it wrote the step before
+        for (int k = 0; k < P.K; ++k) {
+            UpdateOperands<NPL> a;
+            fetch_operands<L, NPL>(Hs, Bpad, dps + (P.per_sweep ? k : 0) * U, zv, 0, j, a);
+            zv[0] = coordinate_update<L, NPL, BOX>(a.h, a.dp, a.zo, beta, r);
+            sweep_done(k);
+        }
+    } else {
+        // The K*U updates as one sequence, two operand buffers: the LDS reads of
+        // the next update are in flight while the current one computes.  With
+        // U >= 2 the next update never reads the z_u the current one writes.
+        UpdateOperands<NPL> a, b;
+        int k = 0, u = 0;
+        fetch_operands<L, NPL>(Hs, Bpad, dps, zv, 0, j, a);
+        for (;;) {
+            int kn = k, un = u + 1;
+            if (un == U) { un = 0; ++kn; }
+            if (kn < P.K)
+                fetch_operands<L, NPL>(Hs, Bpad, dps + (P.per_sweep ? kn : 0) * U, zv, un, j, b);
+            zv[u] = coordinate_update<L, NPL, BOX>(a.h, a.dp, a.zo, beta, r);
+            if (un == 0) sweep_done(k);
+            if (kn == P.K) break;
+            k = kn;
+            u = un;
+            kn = k;
+            un = u + 1;
+            if (un == U) { un = 0; ++kn; }
+            if (kn < P.K)
+                fetch_operands<L, NPL>(Hs, Bpad, dps + (P.per_sweep ? kn : 0) * U, zv, un, j, a);
+            zv[u] = coordinate_update<L, NPL, BOX>(b.h, b.dp, b.zo, beta, r);
+            if (un == 0) sweep_done(k);
+            if (kn == P.K) break;
+            k = kn;
+            u = un;
+        }
     }
 
     if (!active) return;
-    const float lamK = P.lambda ? P.lambda[P.K - 1] : P.lam_default;
-    const float2 *dpK = dps + (P.per_sweep ? P.K - 1 : 0) * U;
-    const float sqEs = sqrtf(P.Es), scale = qam_scale(P.Q);
-    for (int u = j; u < U; u += L) {
-        const float2 zu = zv[u];
-        if (P.z) P.z[(long)v * U + u] = zu;
-        if (!P.llr) continue;
-        float mu, rho;
-        gain_sinr(P, lamK, sm.g[slot * U + u], dpK[u].y, &mu, &rho);
-        float out[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (rho > 0.f && mu > 0.f) {
-            const float s = 1.0f / (mu * sqEs);
-            const float xr = zu.x * s, xi = zu.y * s;
-            if (P.Q == 2) user_llr<1>(xr, xi, scale, rho, out);
-            else if (P.Q == 4) user_llr<2>(xr, xi, scale, rho, out);
-            else user_llr<3>(xr, xi, scale, rho, out);
+    // outputs: lanes of the group take users (z) and (user, axis) pairs (LLRs)
+    if (P.z) {
+        float2 *zt = P.z + (size_t)tile.vbase * U;   // workgroup-uniform base
+        for (int u = j; u < U; u += L) zt[grp * U + u] = zv[u];
+    }
+    if (P.llr) {
+        const int Q = P.Q, half = Q >> 1;
+        float *lt = P.llr + (size_t)tile.vbase * U * Q;
+        const float2 *lcs = sm.lc + (size_t)slot * U;
+        for (int idx = j; idx < 2 * U; idx += L) {
+            const int u = idx >> 1, ax = idx & 1;
+            const float2 zu = zv[u], co = lcs[u];
+            const float t = (ax ? zu.y : zu.x) * co.x;
+            float *dst = lt + (grp * U + u) * Q + ax * half;
+            if (half == 3) axis_llrs<3>(t, co.y, dst);
+            else if (half == 2) axis_llrs<2>(t, co.y, dst);
+            else axis_llrs<1>(t, co.y, dst);
         }
-        float *dst = P.llr + ((long)v * U + u) * P.Q;
-        for (int b = 0; b < P.Q; ++b) dst[b] = out[b];
     }
 }
 
