@@ -62,6 +62,9 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+TRAFFIC_TAG = "ocd_forward_b128_u8_w1200_s14_64qam_k3"
+
+
 def read_traffic(kernel_tag):
     """Measured HBM bytes per launch from a committed rocprofv3 counter summary,
     if it was taken on the current kernel sources; else None."""
@@ -154,6 +157,105 @@ def cpu_baseline(wl_host, K, Q, N0, target_s):
             "vectors_per_s": W * S * reps / dt}
 
 
+# ------------------------------------------------------------------ rocprofv3 summaries
+
+COPY_BYTES = 256 << 20   # the --calibrate-copy transfer
+
+
+def _csv_rows(d, suffix):
+    import csv
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError("none of %s in rocprofv3 CSV columns %s" % (names, sorted(row)))
+
+
+def _kernel_key(row):
+    name = _col(row, "Kernel_Name", "Name").split("(")[0]
+    grid = int(_col(row, "Grid_Size_X", "Grid_Size"))
+    wg = int(_col(row, "Workgroup_Size_X", "Workgroup_Size"))
+    return name, grid, wg
+
+
+def summarize_profile(dirs, traffic_out, command):
+    """Prints the rocprofv3 --stats table and a per-(kernel, grid, workgroup) breakdown
+    of the kernel trace; on --pmc FETCH_SIZE / WRITE_SIZE directories prints the
+    per-dispatch counters, scales them by what the same counters read for the
+    256 MiB calibration copy and (with traffic_out) writes the per-launch bytes of
+    the detection kernel."""
+    import statistics
+    out = []
+    counters = {}
+    for d in dirs:
+        stats = _csv_rows(d, "kernel_stats.csv")
+        if stats:
+            out.append("rocprofv3 --stats (%s):" % os.path.basename(d.rstrip("/")))
+            out.append("%-60s %8s %12s %12s %12s" % ("kernel", "calls", "avg_us", "min_us", "max_us"))
+            for r in sorted(stats, key=lambda r: -float(_col(r, "TotalDurationNs"))):
+                out.append("%-60s %8s %12.3f %12.3f %12.3f" % (
+                    _col(r, "Name")[:60], _col(r, "Calls"), float(_col(r, "AverageNs")) / 1e3,
+                    float(_col(r, "MinNs")) / 1e3, float(_col(r, "MaxNs")) / 1e3))
+        trace = _csv_rows(d, "kernel_trace.csv")
+        if trace:
+            per = {}
+            for r in trace:
+                dur = int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))
+                per.setdefault(_kernel_key(r), []).append(dur)
+            out.append("kernel trace by launch shape (%s):" % os.path.basename(d.rstrip("/")))
+            out.append("%-60s %9s %5s %7s %10s %10s" % ("kernel", "grid", "wg", "calls", "mean_us",
+                                                        "median_us"))
+            for (name, grid, wg), v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+                out.append("%-60s %9d %5d %7d %10.3f %10.3f" % (
+                    name[:60], grid, wg, len(v), statistics.mean(v) / 1e3,
+                    statistics.median(v) / 1e3))
+        for r in _csv_rows(d, "counter_collection.csv"):
+            cname = _col(r, "Counter_Name")
+            counters.setdefault(cname, {}).setdefault(_kernel_key(r), []).append(
+                float(_col(r, "Counter_Value")))
+    traffic = {}
+    for cname, per in sorted(counters.items()):
+        # calibration: the largest copy kernel dispatch is the 256 MiB copy
+        copies = [(max(v), k) for k, v in per.items() if "copyBuffer" in k[0] or "copy" in k[0].lower()]
+        cal = max(copies)[0] if copies else None
+        scale = COPY_BYTES / (cal * 1024.0) if cal else None
+        out.append("%s (KiB per dispatch; calibration copy of %d MiB reads %s KiB -> scale %s):" % (
+            cname, COPY_BYTES >> 20, cal, "%.4f" % scale if scale else None))
+        for (name, grid, wg), v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+            med = statistics.median(v)
+            out.append("  %-58s grid=%-8d wg=%-4d n=%-4d median=%.1f KiB  scaled=%.3f MB" % (
+                name[:58], grid, wg, len(v), med, med * 1024 * (scale or 0) / 1e6))
+            if "k_forward" in name:
+                traffic.setdefault(cname, []).append((len(v), name, grid, wg, med, scale))
+    print("\n".join(out))
+    if traffic_out:
+        if "FETCH_SIZE" not in traffic or "WRITE_SIZE" not in traffic:
+            print("no FETCH_SIZE/WRITE_SIZE dispatches of the detection kernel", file=sys.stderr)
+            return 1
+        f = max(traffic["FETCH_SIZE"])
+        w = max(traffic["WRITE_SIZE"])
+        rec = {
+            "kernel": f[1], "grid": f[2], "workgroup": f[3],
+            "workload": "B=128 U=8, 1200 subcarriers x 14 symbols, 64-QAM, K=3, MMSE, FP32",
+            "fetch_kib_per_launch": f[4], "fetch_scale": f[5],
+            "write_kib_per_launch": w[4], "write_scale": w[5],
+            "bytes_per_launch": f[4] * 1024 * f[5] + w[4] * 1024 * w[5],
+            "source_hash": source_hash(),
+            "command": command,
+        }
+        with open(traffic_out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print("wrote %s: %.3f MB per launch" % (traffic_out, rec["bytes_per_launch"] / 1e6))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,7 +267,19 @@ def main():
                     help="only the headline workload (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
+    ap.add_argument("--plan", default=None,
+                    help="L,VPB[,XCD]: fix the launch plan instead of autotuning (profiled runs, "
+                         "so that every traced launch of the kernel is the timed one)")
+    ap.add_argument("--summarize-profile", nargs="+", metavar="DIR", default=None,
+                    help="no GPU work: summarise rocprofv3 CSV output (a --kernel-trace --stats "
+                         "directory, or FETCH_SIZE and WRITE_SIZE --pmc directories) and exit")
+    ap.add_argument("--traffic-out", default=None,
+                    help="with --summarize-profile on counter directories: write the HBM traffic "
+                         "summary that fills roofline.traffic")
+    ap.add_argument("--command", default="", help="with --summarize-profile: the profiled command")
     args = ap.parse_args()
+    if args.summarize_profile:
+        sys.exit(summarize_profile(args.summarize_profile, args.traffic_out, args.command))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (subcarriers would be "
@@ -201,24 +315,35 @@ def main():
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
     outs = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
              torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
-    plan = ocd.ocd_autotune(pb, slots[0]["H"], slots[0]["y"], outs[0][0], outs[0][1], repeats=5)
-    log("autotuned plan %s" % plan.as_dict())
+    if args.plan:
+        f = [int(x) for x in args.plan.split(",")] + [0]
+        plan = ocd.Plan(f[0], f[1], f[2], 0)
+        ocd.ocd_set_plan(pb, plan)
+        log("fixed plan %s" % plan.as_dict())
+    else:
+        plan = ocd.ocd_autotune(pb, slots[0]["H"], slots[0]["y"], outs[0][0], outs[0][1],
+                                repeats=5)
+        log("autotuned plan %s" % plan.as_dict())
 
     def step_fn(i, prob=pb, ins=slots, o=outs):
         return lambda: ocd.ocd_detect(prob, ins[i]["H"], ins[i]["y"], z=o[i][0], llr=o[i][1])
 
     fns = [step_fn(i) for i in range(len(slots))]
-    t_kernel = kernel_durations(torch, fns)
+    t_single = kernel_durations(torch, fns)
     gs = GraphedSteps(torch, fns)
     log("timing %d steps" % args.steps)
     t_step, nsteps = time_graph(torch, gs, args.steps, args.warmup)
+    # one launch per step: the kernel's average launch duration over the timed
+    # region (HIP events on the stream the graph replays on)
+    t_kernel = t_step
     nvec = W * S
     bits_per_step = nvec * U * Q
     flops_v, bytes_v = algorithmic(B, U, S, K, Q)
     value = bits_per_step / t_step / 1e9
     hbm_gbps = bytes_v * nvec / t_step / 1e9
     ach_tflops = flops_v * nvec / t_kernel / 1e12
-    log("%.3f us/step, %.2f Gb/s, kernel %.3f us" % (t_step * 1e6, value, t_kernel * 1e6))
+    log("%.3f us/step, %.2f Gb/s, single eager launch %.3f us" % (t_step * 1e6, value,
+                                                                  t_single * 1e6))
 
     # spot parity of the timed outputs against the FP64 oracle (sampled subcarriers)
     import oracle
@@ -238,7 +363,7 @@ def main():
     fwd_kernel = "ocd::k_forward<%d, %d, false, false>" % (plan.lanes_per_vector,
                                                           max(2, 1 << math.ceil(math.log2(
                                                               max(2, math.ceil(B / plan.lanes_per_vector))))))
-    traffic = read_traffic("ocd_forward_config2")
+    traffic = read_traffic(TRAFFIC_TAG)
     result = {
         "metric": "detected Gb/s & % HBM peak (B=128,U=8,64QAM,K=3); fwd+bwd vectors/s",
         "value": value,
@@ -271,6 +396,8 @@ def main():
             "frac_of_nonpacked_fp32": ach_tflops / FP32_NONPACKED_TFLOPS,
             "traffic": traffic,
             "avg_kernel_us": t_kernel * 1e6,
+            "avg_kernel_us_source": "HIP events around the timed graph replays / launches",
+            "single_eager_launch_us": t_single * 1e6,
             "flops_per_vector": flops_v,
             "bytes_per_vector": bytes_v,
             "vectors_per_launch": nvec,
@@ -422,7 +549,7 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     }
     del Hs, ys, z, L, zs, Ls, ws, gs, call
 
-    # ---- differentiable form: forward + backward step, config 5 shape
+    # ---- differentiable form: forward + backward step (B=128, U=16, 2048 x 4, 16-QAM, K=4)
     log("form: forward+backward")
     B5, U5, W5, S5, Q5, K5 = 128, 16, 2048, 4, 4, 4
     wl = synth.make_workload_device(B5, U5, W5, S5, Q5, 10.0, seed=4000, device=dev)

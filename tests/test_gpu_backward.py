@@ -39,7 +39,8 @@ def _bce(L, bits):
 
 
 def _case(ocd, mode, B=128, U=16, W=32, S=4, Q=4, K=4, snr=10.0, seed=0):
-    """Config-5 slice: 32 subcarriers x 4 symbols, 16-QAM, K=4, 10 dB."""
+    """Slice of the differentiable workload: B=128, U=16, 32 subcarriers x 4 symbols,
+    16-QAM, K=4, 10 dB."""
     say("backward case mode=%s B=%d U=%d W=%d S=%d Q=%d K=%d" % (mode, B, U, W, S, Q, K))
     wl = synth.make_workload(B, U, W, S, Q, snr, seed=[20, seed])
     N0 = f32(wl["N0"])

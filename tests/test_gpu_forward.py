@@ -54,19 +54,19 @@ def run_and_compare(ocd, B, U, W, S, Q, K, mode, snr, seed, lam=None, beta=0.0, 
     return wl, z, L
 
 
-# config 1 (B=32, U=8, 64 subcarriers, 16-QAM, 10 dB, K=3) under every lane split
+# B=32, U=8, 64 subcarriers, 16-QAM, 10 dB, K=3 under every lane split
 @pytest.mark.parametrize("plan", [(4, 16, 0), (4, 1, 0), (4, 3, 1), (8, 64, 0), (8, 7, 0),
                                   (16, 32, 1), (16, 5, 0), (32, 16, 0), (32, 2, 0)])
-def test_config1_every_plan(ocd, plan):
+def test_b32_u8_every_plan(ocd, plan):
     run_and_compare(ocd, 32, 8, 64, 1, 4, 3, "mmse", 10.0, [1, 0, 0], hist=True, plan=plan)
 
 
-def test_config1_default_plan(ocd):
+def test_b32_u8_default_plan(ocd):
     # W differs from the forced-plan cases above, so the heuristic plan is used
     run_and_compare(ocd, 32, 8, 63, 1, 4, 3, "mmse", 10.0, [1, 0, 1], hist=True)
 
 
-def test_config2_full_slot(ocd):
+def test_b128_u8_64qam_full_slot(ocd):
     """B=128, U=8, 1200 subcarriers x 14 symbols, 64-QAM, K=3, MMSE, 20 dB: the whole
     slot against the oracle (the workload the benchmark times)."""
     wl, z, L = run_and_compare(ocd, 128, 8, 1200, 14, 6, 3, "mmse", 20.0, [2, 0, 0])
@@ -82,13 +82,13 @@ def test_config2_full_slot(ocd):
 
 
 @pytest.mark.parametrize("plan", [(4, 14, 0), (4, 16, 1), (8, 28, 0), (8, 64, 1), (16, 32, 0)])
-def test_config2_slice_plans(ocd, plan):
+def test_b128_u8_64qam_slice_plans(ocd, plan):
     run_and_compare(ocd, 128, 8, 60, 14, 6, 3, "mmse", 20.0, [2, 1, 0], plan=plan)
 
 
 @pytest.mark.parametrize("Q", [2, 4])
 @pytest.mark.parametrize("snr", [0.0, 10.0, 20.0])
-def test_config3_box(ocd, Q, snr):
+def test_b256_u32_box(ocd, Q, snr):
     """B=256, U=32, 14 symbols per subcarrier, box at the constellation edge, K=5."""
     run_and_compare(ocd, 256, 32, 24, 14, Q, 5, "box", snr, [3, int(snr), Q])
 
