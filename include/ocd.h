@@ -135,15 +135,22 @@ ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void 
                                void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* A launch plan: how vectors map onto lanes and workgroups.
- *   lanes_per_vector   lanes that share one (subcarrier, symbol) vector: 4, 8, 16 or 32
- *   vectors_per_block  vectors per workgroup (1..512/lanes_per_vector); H of every
- *                      subcarrier a workgroup touches is staged once into LDS
- *   xcd_remap          1: consecutive tiles go to the same XCD (shared L2) */
+ *   lanes_per_vector      lanes that share one (subcarrier, symbol) vector: 4, 8, 16 or 32
+ *                         (16 or 32 with channel_in_registers)
+ *   vectors_per_block     vectors per workgroup: 1..512/lanes_per_vector, or
+ *                         1..256/lanes_per_vector with channel_in_registers
+ *   xcd_remap             1: consecutive tiles go to the same XCD (shared L2)
+ *   channel_in_registers  0: the H_w of every subcarrier a workgroup touches is staged
+ *                         once into LDS and shared by its vectors (the choice when many
+ *                         symbols share H_w); 1: each vector's lane group keeps the
+ *                         columns of its H_w in registers and nothing is staged (the
+ *                         choice when few do).  1 needs U <= 8 and B <= 8 * lanes_per_vector,
+ *                         and is forward-only. */
 typedef struct {
     int lanes_per_vector;
     int vectors_per_block;
     int xcd_remap;
-    int reserved;
+    int channel_in_registers;
 } ocd_plan;
 
 /* The plan ocd_detect would use for this problem (cached or heuristic). */

@@ -63,14 +63,17 @@ class Problem(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    """``ocd_plan``: lanes per vector, vectors per workgroup, XCD remap."""
+    """``ocd_plan``: lanes per vector, vectors per workgroup, XCD remap, and whether
+    each vector keeps its channel columns in registers instead of sharing an
+    LDS-staged H_w."""
 
     _fields_ = [("lanes_per_vector", ctypes.c_int), ("vectors_per_block", ctypes.c_int),
-                ("xcd_remap", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int)]
 
     def as_dict(self):
         return {"lanes_per_vector": self.lanes_per_vector,
-                "vectors_per_block": self.vectors_per_block, "xcd_remap": self.xcd_remap}
+                "vectors_per_block": self.vectors_per_block, "xcd_remap": self.xcd_remap,
+                "channel_in_registers": self.channel_in_registers}
 
 
 class OCDError(RuntimeError):

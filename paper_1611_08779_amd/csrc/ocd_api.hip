@@ -110,6 +110,14 @@ int npl_for(int B, int L)
 
 // Fills the launch parameters of a (problem, plan) pair; false if the plan is
 // not valid for the problem (group too small for B, LDS too small, ...).
+// Channel-in-registers plans: the compile-time bound on U the kernel is built
+// for (8), 0 if the problem does not fit (U <= 8 and at most 64 complex entries
+// of H_w per lane, so that everything stays in registers).
+static int reg_user_bound(int U, int npl)
+{
+    return (U <= 8 && npl <= 8) ? 8 : 0;
+}
+
 bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda, bool backward,
                  Params &P, int &npl, int &threads, size_t &lds)
 {
@@ -117,7 +125,9 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
     if (L != 4 && L != 8 && L != 16 && L != 32) return false;
     npl = npl_for(pb->B, L);
     if (!npl) return false;
-    const int cap = 512 / L;
+    const bool reg = pl.channel_in_registers != 0;
+    if (reg && (backward || (L != 16 && L != 32) || !reg_user_bound(pb->U, npl))) return false;
+    const int cap = (reg ? 256 : 512) / L;
     if (pl.vectors_per_block < 1 || pl.vectors_per_block > cap) return false;
     std::memset(&P, 0, sizeof(P));
     P.B = pb->B; P.U = pb->U; P.W = pb->W; P.S = pb->S; P.K = pb->K; P.Q = pb->Q;
@@ -142,6 +152,12 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
     P.nblocks = (int)((nvec + P.vpb - 1) / P.vpb);
     const int waves = (P.vpb * L + 63) / 64;
     threads = waves * 64;
+    if (reg) {
+        P.reg_uc = reg_user_bound(pb->U, npl);
+        P.maxslots = 0;
+        lds = 0;
+        return true;
+    }
     lds = lds_bytes(P, threads / L, backward);
     return lds <= (size_t)lds_limit_bytes();
 }
@@ -161,8 +177,18 @@ static double plan_score(const ocd_problem *pb, const ocd_plan &pl, const Params
     return blocks * threads * useful * eff;
 }
 
-ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backward)
+ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backward, bool allow_reg)
 {
+    if (allow_reg && !backward && pb->S <= 2) {
+        // a channel shared by at most two vectors: nothing to reuse from LDS
+        for (int L : {16, 32}) {
+            ocd_plan pl = {L, 256 / L, 0, 1};
+            Params P;
+            int npl, threads;
+            size_t lds;
+            if (make_params(pb, pl, lambda, backward, P, npl, threads, lds)) return pl;
+        }
+    }
     int L = 4;
     while (L < 32 && L * 16 < pb->B) L *= 2;
     ocd_plan best = {L, 1, 0, 0};
@@ -214,8 +240,10 @@ static void load_plan_file_locked()
         char key[256];
         ocd_plan pl = {0, 0, 0, 0};
         if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"lanes_per_vector\": %d, "
-                              "\"vectors_per_block\": %d, \"xcd_remap\": %d",
-                        key, &pl.lanes_per_vector, &pl.vectors_per_block, &pl.xcd_remap) == 4)
+                              "\"vectors_per_block\": %d, \"xcd_remap\": %d, "
+                              "\"channel_in_registers\": %d",
+                        key, &pl.lanes_per_vector, &pl.vectors_per_block, &pl.xcd_remap,
+                        &pl.channel_in_registers) == 5)
             g_plans[key] = pl;
     }
     std::fclose(f);
@@ -230,9 +258,9 @@ static void save_plan_file_locked()
     if (!f) return;
     for (auto &kv : g_plans)
         std::fprintf(f, "{\"key\": \"%s\", \"lanes_per_vector\": %d, \"vectors_per_block\": %d, "
-                        "\"xcd_remap\": %d}\n",
+                        "\"xcd_remap\": %d, \"channel_in_registers\": %d}\n",
                      kv.first.c_str(), kv.second.lanes_per_vector, kv.second.vectors_per_block,
-                     kv.second.xcd_remap);
+                     kv.second.xcd_remap, kv.second.channel_in_registers);
     std::fclose(f);
     std::rename(tmp.c_str(), path);
 }
@@ -264,7 +292,7 @@ ocd_plan choose_plan(const ocd_problem *pb, const float *lambda, bool backward)
         size_t lds;
         if (make_params(pb, pl, lambda, backward, P, npl, threads, lds)) return pl;
     }
-    return heuristic_plan(pb, lambda, backward);
+    return heuristic_plan(pb, lambda, backward, true);
 }
 
 static bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -316,8 +344,16 @@ ocd_status run_forward(const ocd_problem *pb, const ocd_plan &pl, const void *H,
     P.llr = llr;
     P.z_hist = reinterpret_cast<float2 *>(z_hist);
     set_vec_ok(P, pb, H, y);
-    hipError_t e = launch_forward(pl.lanes_per_vector, npl, pb->storage == OCD_STORE_F16, P,
-                                  threads, lds, stream);
+    if (pl.channel_in_registers && (!P.vec_ok || g)) {
+        // the register kernel takes aligned rows of even length and fuses the
+        // preprocessing: anything else runs an LDS-staged plan
+        return run_forward(pb, heuristic_plan(pb, lambda, false, false), H, y, lambda, g, dinv, p,
+                           z, llr, z_hist, stream);
+    }
+    const bool f16 = pb->storage == OCD_STORE_F16;
+    hipError_t e = pl.channel_in_registers
+                       ? launch_forward_reg(pl.lanes_per_vector, npl, P.reg_uc, f16, P, threads, stream)
+                       : launch_forward(pl.lanes_per_vector, npl, f16, P, threads, lds, stream);
     return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
 }
 
@@ -367,7 +403,7 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
     if (st != OCD_OK) return st;
     if (!H || !y || !z || !llr || !best) return OCD_EINVAL;
     if (pb->W == 0) {
-        *best = heuristic_plan(pb, nullptr, false);
+        *best = heuristic_plan(pb, nullptr, false, true);
         return OCD_OK;
     }
     repeats = std::max(1, std::min(repeats, 100));
@@ -389,6 +425,14 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
                 if (make_params(pb, pl, nullptr, false, P, npl, threads, lds)) cands.push_back(pl);
             }
     }
+    for (int L : {16, 32})   // channel columns in registers (no LDS)
+        for (int v = 256 / L; v >= 1 && v >= 64 / L; v /= 2) {
+            ocd_plan pl = {L, v, 0, 1};
+            Params P;
+            int npl, threads;
+            size_t lds;
+            if (make_params(pb, pl, nullptr, false, P, npl, threads, lds)) cands.push_back(pl);
+        }
     if (cands.empty()) return OCD_EUNSUPPORTED;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OCD_EDEVICE;

@@ -16,7 +16,7 @@ int npl_for(int B, int L);
 bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda, bool backward,
                  Params &P, int &npl, int &threads, size_t &lds);
 void set_vec_ok(Params &P, const ocd_problem *pb, const void *H, const void *y);
-ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backward);
+ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backward, bool allow_reg);
 ocd_plan choose_plan(const ocd_problem *pb, const float *lambda, bool backward);
 std::string plan_key(const ocd_problem *pb, bool per_sweep, bool backward);
 bool cached_plan(const std::string &key, ocd_plan &pl);

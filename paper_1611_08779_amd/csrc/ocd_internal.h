@@ -19,6 +19,7 @@ struct Params {
     int xcd_remap;
     int vec_ok;      // vector loads allowed (B even, 16-byte aligned bases)
     int nblocks;
+    int reg_uc;      // channel-in-registers plans: compile-time bound on U (else 0)
     float Es, N0, beta;
     float lam_default;   // regulariser when lambda == nullptr
     float sqEs;          // sqrt(Es)
@@ -65,6 +66,8 @@ hipError_t launch_forward(int L, int NPL, bool f16, const Params &p, int threads
                           hipStream_t s);
 hipError_t launch_backward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
                            hipStream_t s);
+hipError_t launch_forward_reg(int L, int NPL, int UC, bool f16, const Params &p, int threads,
+                              hipStream_t s);
 hipError_t launch_preprocess(bool f16, const Params &p, float *g, float *dinv, float *pp,
                              hipStream_t s);
 hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s);

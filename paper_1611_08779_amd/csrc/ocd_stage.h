@@ -191,6 +191,17 @@ __device__ __forceinline__ float2 llr_coef(const Params &P, float g, float pK, f
     return make_float2(1.0f / (mu * P.sqEs * P.qscale), rho * P.qscale * P.qscale);
 }
 
+// Soft output of one axis of one user: t = the axis of z_u times a, c = the
+// LLR scale (llr_coef); writes the HALF LLRs of that axis, MSB first.
+template <int HALF>
+__device__ __forceinline__ void axis_llrs(float t, float c, float *dst)
+{
+    float D[HALF];
+    pam_metrics<HALF>(t, D);
+#pragma unroll
+    for (int b = 0; b < HALF; ++b) dst[b] = c * D[b];
+}
+
 // Algorithm 1's preprocessing once per staged subcarrier (or a copy of the
 // precomputed values): g_u = ||h_u||^2, d_u^-1 = (g_u + lambda_k)^-1 (0 if that
 // is 1/0), p_u = d_u^-1 g_u.  Ends with a workgroup barrier, after which the
@@ -325,21 +336,28 @@ __device__ __forceinline__ void fetch_operands(const float2 *Hs, int Bpad, const
     o.zo = zv[u];
 }
 
-// conj(h)^T r over this lane's entries.  One accumulator per component: the
-// real and imaginary chains alternate, which keeps dependent FMAs two issue
-// slots apart (their latency), and there is no final merge.
-template <int NPL>
+// conj(h)^T r over this lane's entries with CHAINS accumulators per component.
+// One chain: the real and imaginary chains alternate, which keeps dependent FMAs
+// two issue slots apart (their latency), and there is no final merge -- the
+// choice when several waves share a SIMD.  Two chains halve the dependency
+// depth for one merge per component -- the choice when few waves do.
+template <int NPL, int CHAINS = 1>
 __device__ __forceinline__ float2 partial_inner(const float2 *h, const float2 *r)
 {
-    float ar = 0.f, ai = 0.f;
+    static_assert(CHAINS == 1 || (CHAINS == 2 && NPL % 2 == 0), "one or two chains");
+    float ar[CHAINS], ai[CHAINS];
+#pragma unroll
+    for (int c = 0; c < CHAINS; ++c) ar[c] = ai[c] = 0.f;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-        ar = fmaf(h[i].x, r[i].x, ar);
-        ai = fmaf(h[i].x, r[i].y, ai);
-        ar = fmaf(h[i].y, r[i].y, ar);
-        ai = fmaf(-h[i].y, r[i].x, ai);
+        const int c = i % CHAINS;
+        ar[c] = fmaf(h[i].x, r[i].x, ar[c]);
+        ai[c] = fmaf(h[i].x, r[i].y, ai[c]);
+        ar[c] = fmaf(h[i].y, r[i].y, ar[c]);
+        ai[c] = fmaf(-h[i].y, r[i].x, ai[c]);
     }
-    return make_float2(ar, ai);
+    if constexpr (CHAINS == 2) return make_float2(ar[0] + ar[1], ai[0] + ai[1]);
+    return make_float2(ar[0], ai[0]);
 }
 
 // r <- r - h * delta (complex), this lane's entries.
@@ -371,11 +389,11 @@ __device__ __forceinline__ void axpy_add(const float2 *h, float2 a, float2 *r)
 // One coordinate update of Algorithm 1 for the lanes of a group:
 //   z_u' = proj(d_u^-1 h_u^H r + p_u z_u),  r <- r - h_u (z_u' - z_u).
 // h: this lane's part of column u; dp = (d_u^-1, p_u); zo = z_u.  Returns z_u'.
-template <int L, int NPL, bool BOX>
+template <int L, int NPL, bool BOX, int CHAINS = 1>
 __device__ __forceinline__ float2 coordinate_update(const float2 *h, float2 dp, float2 zo,
                                                     float beta, float2 *r)
 {
-    float2 ip = partial_inner<NPL>(h, r);
+    float2 ip = partial_inner<NPL, CHAINS>(h, r);
     ip.x = group_sum<L>(ip.x);
     ip.y = group_sum<L>(ip.y);
     float cr = fmaf(dp.x, ip.x, dp.y * zo.x);

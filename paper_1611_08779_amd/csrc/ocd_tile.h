@@ -16,17 +16,6 @@
 
 namespace ocd {
 
-// Soft output of one axis of one user: t = the axis of z_u times a, c = the
-// LLR scale (llr_coef); writes the HALF LLRs of that axis, MSB first.
-template <int HALF>
-__device__ __forceinline__ void axis_llrs(float t, float c, float *dst)
-{
-    float D[HALF];
-    pam_metrics<HALF>(t, D);
-#pragma unroll
-    for (int b = 0; b < HALF; ++b) dst[b] = c * D[b];
-}
-
 // Algorithm 1 and the soft output for the vectors of one tile.  The caller has
 // carved LDS; this function stages H_w and returns after writing z, z_hist and
 // the LLRs.  Every thread of the workgroup must call it (it contains barriers);

@@ -37,7 +37,7 @@ def run_and_compare(ocd, B, U, W, S, Q, K, mode, snr, seed, lam=None, beta=0.0, 
     lam_t = None if lam is None else dev(np.asarray(lam, np.float32))
     if plan is not None:
         pb = ocd.problem(B, U, W, S, Q, K, mode, "f32", N0, Es, beta)
-        ocd.ocd_set_plan(pb, ocd.Plan(*plan, 0))
+        ocd.ocd_set_plan(pb, ocd.Plan(*(tuple(plan) + (0,) * (4 - len(plan)))))
     z, L, zh = ocd.detect(dev(wl["H"]), dev(wl["y"]), K, Q, mode, N0, Es, beta, lam=lam_t,
                           want_hist=hist)
     torch.cuda.synchronize()
@@ -120,6 +120,60 @@ def test_channel_too_large_for_lds_is_rejected(ocd):
     with pytest.raises(ocd.OCDError) as ei:
         ocd.detect(H, y, 1, 2, "box", 0.1)
     assert ei.value.status == -2
+
+
+# channel columns held in registers (no LDS): the plans for channels few symbols share
+REG_CASES = [
+    # B, U, W, S, Q, K, mode, plan (L, vectors per workgroup, xcd, channel_in_registers)
+    (128, 8, 300, 1, 6, 3, "mmse", (16, 16, 0, 1)),   # one H per vector, 64-QAM (a slice)
+    (128, 8, 97, 1, 6, 3, "mmse", (32, 8, 0, 1)),     # ragged last workgroup
+    (128, 6, 40, 2, 4, 4, "box", (16, 4, 0, 1)),      # U below the register bound, S = 2
+    (100, 5, 30, 1, 2, 2, "box", (32, 3, 0, 1)),      # padded lanes (B < L * NPL)
+    (64, 8, 50, 3, 4, 3, "mmse", (16, 16, 0, 1)),     # NPL = 4, three vectors per subcarrier
+    (33, 4, 20, 1, 4, 2, "mmse", (16, 7, 0, 1)),      # odd B: scalar loads
+    (32, 8, 64, 1, 4, 3, "mmse", (16, 16, 0, 1)),     # NPL = 2
+    (256, 1, 12, 1, 6, 5, "box", (32, 2, 0, 1)),      # one user, NPL = 8 at L = 32
+]
+
+
+@pytest.mark.parametrize("case", REG_CASES, ids=[str(c[:7]) for c in REG_CASES])
+def test_channel_in_registers_plans(ocd, case):
+    B, U, W, S, Q, K, mode, plan = case
+    run_and_compare(ocd, B, U, W, S, Q, K, mode, 12.0, [12] + list(case[:6]), hist=True, plan=plan)
+
+
+def test_channel_in_registers_hybrid_and_preprocessed(ocd):
+    """Per-sweep regularisers on the register path (S = 1 selects it by default); with
+    caller-supplied preprocessing the same plan runs LDS-staged (the register kernel
+    fuses the preprocessing)."""
+    K = 4
+    lam = np.array([0.3, 0.05, 0.12, 0.08], np.float32)
+    run_and_compare(ocd, 128, 8, 40, 1, 4, K, "hybrid", 10.0, [12, 1], lam=lam, beta=0.9, hist=True)
+    wl = synth.make_workload(128, 8, 50, 1, 6, 20.0, seed=[12, 2])
+    N0 = f32(wl["N0"])
+    H, y = dev(wl["H"]), dev(wl["y"])
+    pb = ocd.problem(128, 8, 50, 1, 6, 3, "mmse", "f32", N0)
+    assert ocd.ocd_get_plan(pb).channel_in_registers == 1
+    g, dinv, p = ocd.preprocess(H, 3, 6, "mmse", N0)
+    z2, L2, _ = ocd.detect(H, y, 3, 6, "mmse", N0, pre=(g, dinv, p))
+    torch.cuda.synchronize()
+    zo, Lo, _ = oracle_ref(wl["H"], wl["y"], 3, 6, "mmse", N0)
+    assert z_rel_err(host(z2), zo) <= Z_TOL_F32
+    assert llr_rel_err(host(L2), Lo) <= LLR_TOL_F32
+
+
+def test_channel_in_registers_fp16(ocd):
+    B, U, W, S, Q, K = 128, 8, 80, 1, 6, 3
+    wl = synth.make_workload(B, U, W, S, Q, 15.0, seed=[12, 3])
+    N0 = f32(wl["N0"])
+    H16, y16 = to_f16_pairs(wl["H"]), to_f16_pairs(wl["y"])
+    pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f16", N0)
+    ocd.ocd_set_plan(pb, ocd.Plan(32, 8, 0, 1))
+    z, L, _ = ocd.detect(dev(H16), dev(y16), K, Q, "mmse", N0, storage="f16")
+    torch.cuda.synchronize()
+    zo, Lo, _ = oracle_ref(from_f16_pairs(H16), from_f16_pairs(y16), K, Q, "mmse", N0)
+    assert z_rel_err(host(z), zo) <= Z_TOL_F32
+    assert llr_rel_err(host(L), Lo) <= LLR_TOL_F32
 
 
 def test_hybrid_per_sweep_regulariser(ocd):
