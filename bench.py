@@ -565,6 +565,9 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     wsb = torch.empty(ocd.ocd_backward_workspace_bytes(pb5), dtype=torch.uint8, device=dev)
     bits = wl["bits"].float()
     inv_n = 1.0 / bits.numel()
+    z5 = torch.empty(W5, S5, U5, dtype=torch.complex64, device=dev)
+    ocd.ocd_autotune(pb5, wl["H"], wl["y"], z5, L5, repeats=3)
+    del z5
 
     def fwd_bwd():
         ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)

@@ -156,12 +156,13 @@ typedef struct {
 /* The plan ocd_detect would use for this problem (cached or heuristic). */
 ocd_status ocd_get_plan(const ocd_problem *pb, ocd_plan *plan);
 
-/* Force a plan for this problem's shape (B, U, S, K, Q, mode, storage). */
+/* Force a plan for this problem's shape (B, U, W, S, K, Q, mode, storage), with and
+ * without per-sweep regularisers (the backward pass keeps its own choice). */
 ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
 
 /* Autotuner: times every valid plan for this problem on the caller's buffers
  * (outputs are overwritten; z and llr must be non-NULL), caches the fastest
- * for the shape and returns it.  Synchronises `stream`.  When the environment
+ * for the shape (with and without per-sweep regularisers) and returns it.  Synchronises `stream`.  When the environment
  * variable OCD_TUNE_CACHE names a file, plans are also loaded from and saved
  * to that JSON file, keyed by GPU architecture and shape. */
 ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,

@@ -393,6 +393,7 @@ extern "C" ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan)
     size_t lds;
     if (!make_params(pb, *plan, nullptr, false, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
     store_plan(plan_key(pb, false, false), *plan, false);
+    store_plan(plan_key(pb, true, false), *plan, false);
     return OCD_OK;
 }
 
@@ -455,7 +456,10 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != OCD_OK) return st;
+    // the same kernels run with and without per-sweep regularisers (only the
+    // preprocessing table is longer): the plan serves both
     store_plan(plan_key(pb, false, false), best_pl, true);
+    store_plan(plan_key(pb, true, false), best_pl, true);
     *best = best_pl;
     return OCD_OK;
 }

@@ -56,12 +56,16 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
         if (P.z_hist && active)
             for (int u = j; u < U; u += L) P.z_hist[((long)v * P.K + k) * U + u] = zv[u];
     };
-    if (U == 1) {
-        // a single user: every update reads the z it wrote the step before
+    if (U == 1 || NPL > 8) {
+        // a single user: every update reads the z it wrote the step before; with
+        // more than 8 entries per lane a second operand buffer would cost more
+        // occupancy than it hides latency
         for (int k = 0; k < P.K; ++k) {
-            UpdateOperands<NPL> a;
-            fetch_operands<L, NPL>(Hs, Bpad, dps + (P.per_sweep ? k : 0) * U, zv, 0, j, a);
-            zv[0] = coordinate_update<L, NPL, BOX>(a.h, a.dp, a.zo, beta, r);
+            for (int u = 0; u < U; ++u) {
+                UpdateOperands<NPL> a;
+                fetch_operands<L, NPL>(Hs, Bpad, dps + (P.per_sweep ? k : 0) * U, zv, u, j, a);
+                zv[u] = coordinate_update<L, NPL, BOX>(a.h, a.dp, a.zo, beta, r);
+            }
             sweep_done(k);
         }
     } else {
