@@ -577,6 +577,11 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     def fwd_only():
         ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
 
+    fwd_only_once = lambda: ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
+    fwd_only_once()
+    dllr0 = (torch.sigmoid(L5) - bits) * inv_n
+    ocd.ocd_autotune_backward(pb5, wl["H"], wl["y"], lam, zh, dllr0, dlam, dbeta, dy, wsb, repeats=3)
+    del dllr0
     tfb, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd] * 8), 400, 16)
     tf, _ = time_graph(torch, GraphedSteps(torch, [fwd_only] * 8), 400, 16)
     fl, _ = algorithmic(B5, U5, S5, K5, Q5)

@@ -168,6 +168,17 @@ ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
 ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,
                         float *z, float *llr, int repeats, ocd_plan *best, hipStream_t stream);
 
+/* Autotuner of the adjoint: times every valid plan of ocd_detect_backward on the
+ * caller's buffers (the outputs dlambda, dbeta, dy are overwritten; the other
+ * arguments are those of ocd_detect_backward), caches the fastest for the shape
+ * and returns it.  Synchronises `stream`.  Plans with channel_in_registers are
+ * forward-only and are not considered. */
+ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const void *y,
+                                 const float *lambda, const float *z_hist, const float *dllr,
+                                 float *dlambda, float *dbeta, float *dy,
+                                 void *workspace, size_t workspace_bytes, int repeats,
+                                 ocd_plan *best, hipStream_t stream);
+
 /* Batched detection of uneven jobs in one launch.
  * Each job j is a full problem (jobs[j]) with its own device arrays H[j], y[j],
  * z[j] (may be NULL) and llr[j] (may be NULL); every job must use the default

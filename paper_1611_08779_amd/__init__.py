@@ -31,7 +31,7 @@ __all__ = [
     "Problem", "Plan", "OCDError", "MODES", "STORAGES", "LIB_PATH",
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_get_plan", "ocd_set_plan",
-    "ocd_autotune", "ocd_jobs_workspace_bytes", "ocd_detect_jobs", "ocd_release_graphs",
+    "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs", "ocd_release_graphs",
     "problem", "detect", "preprocess", "backward", "detect_jobs", "OCD_JOBS_GRAPH", "OCD_JOBS_TUNE",
     "OCD_JOBS_PERSISTENT", "JobsCall",
 ]
@@ -84,7 +84,7 @@ class OCDError(RuntimeError):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libocd.so is not built: run `python -m paper_1611_08779_amd.build` "
+        raise ImportError("libocd.so is not built: run `python paper_1611_08779_amd/build.py` "
                           "(or __graft_entry__.build()) first")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(Problem)
@@ -99,6 +99,8 @@ def _load():
         "ocd_get_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_set_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_autotune": ([P, vp, vp, fp, fp, ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
+        "ocd_autotune_backward": ([P, vp, vp, fp, fp, fp, fp, fp, fp, vp, sz, ctypes.c_int,
+                                   ctypes.POINTER(Plan), vp], ctypes.c_int),
         "ocd_jobs_workspace_bytes": ([P, ctypes.c_int], sz),
         "ocd_detect_jobs": ([P, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(vp), ctypes.c_int, vp, sz, ctypes.c_int, vp], ctypes.c_int),
@@ -247,6 +249,28 @@ def ocd_autotune(pb: Problem, H, y, z, llr, repeats=5, stream=None) -> Plan:
         _dev_ptr(llr, "llr", (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev),
         int(repeats), ctypes.byref(pl), _stream(stream))
     _check("ocd_autotune", st)
+    return pl
+
+
+def ocd_autotune_backward(pb: Problem, H, y, lam, z_hist, dllr, dlam, dbeta, dy, workspace,
+                          repeats=5, stream=None) -> Plan:
+    dev = H.device
+    f32 = (torch.float32,)
+    zt = (torch.complex64, torch.float32)
+    ws_need = ocd_backward_workspace_bytes(pb)
+    pl = Plan()
+    st = _lib.ocd_autotune_backward(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(z_hist, "z_hist", zt, pb.W * pb.S * pb.K * pb.U * 8, dev),
+        _dev_ptr(dllr, "dllr", f32, pb.W * pb.S * pb.U * pb.Q * 4, dev),
+        _dev_ptr(dlam, "dlam", f32, pb.K * 4, dev),
+        _dev_ptr(dbeta, "dbeta", f32, 4, dev),
+        _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
+        _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, int(repeats),
+        ctypes.byref(pl), _stream(stream))
+    _check("ocd_autotune_backward", st)
     return pl
 
 

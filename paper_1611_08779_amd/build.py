@@ -1,4 +1,5 @@
-"""Builds libocd.so (HIP, gfx950) in-tree: ``python -m paper_1611_08779_amd.build``.
+"""Builds libocd.so (HIP, gfx950) in-tree: ``python paper_1611_08779_amd/build.py``
+(run as a script: importing the package would load the library being built).
 
 Every translation unit under ``csrc/`` is compiled with hipcc for gfx950 only,
 with packed-FP32 instruction selection switched off, and linked into

@@ -474,11 +474,11 @@ extern "C" size_t ocd_backward_workspace_bytes(const ocd_problem *pb)
     return (size_t)std::max(1L, nvec) * (size_t)(pb->K + 1) * sizeof(float) + 256;
 }
 
-extern "C" ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void *y,
-                                          const float *lambda, const float *z_hist,
-                                          const float *dllr, float *dlambda, float *dbeta,
-                                          float *dy, void *workspace, size_t workspace_bytes,
-                                          hipStream_t stream)
+namespace ocd {
+
+static ocd_status check_backward_args(const ocd_problem *pb, const void *H, const void *y,
+                                      const float *z_hist, const float *dllr, float *dlambda,
+                                      float *dbeta, void *workspace, size_t workspace_bytes)
 {
     ocd_status st = validate(pb);
     if (st != OCD_OK) return st;
@@ -486,7 +486,14 @@ extern "C" ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, 
     if (pb->W > 0 && (!H || !y || !z_hist || !dllr)) return OCD_EINVAL;
     if (workspace_bytes < ocd_backward_workspace_bytes(pb) || !workspace) return OCD_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace) % 16) return OCD_EINVAL;
-    const ocd_plan pl = choose_plan(pb, lambda, true);
+    return OCD_OK;
+}
+
+static ocd_status run_backward(const ocd_problem *pb, const ocd_plan &pl, const void *H,
+                               const void *y, const float *lambda, const float *z_hist,
+                               const float *dllr, float *dlambda, float *dbeta, float *dy,
+                               void *workspace, hipStream_t stream)
+{
     Params P;
     int npl, threads;
     size_t lds;
@@ -506,4 +513,80 @@ extern "C" ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, 
         e = launch_reduce_partials(P, dlambda, dbeta, stream);
     }
     return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void *y,
+                                          const float *lambda, const float *z_hist,
+                                          const float *dllr, float *dlambda, float *dbeta,
+                                          float *dy, void *workspace, size_t workspace_bytes,
+                                          hipStream_t stream)
+{
+    ocd_status st = check_backward_args(pb, H, y, z_hist, dllr, dlambda, dbeta, workspace,
+                                        workspace_bytes);
+    if (st != OCD_OK) return st;
+    return run_backward(pb, choose_plan(pb, lambda, true), H, y, lambda, z_hist, dllr, dlambda,
+                        dbeta, dy, workspace, stream);
+}
+
+extern "C" ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const void *y,
+                                            const float *lambda, const float *z_hist,
+                                            const float *dllr, float *dlambda, float *dbeta,
+                                            float *dy, void *workspace, size_t workspace_bytes,
+                                            int repeats, ocd_plan *best, hipStream_t stream)
+{
+    ocd_status st = check_backward_args(pb, H, y, z_hist, dllr, dlambda, dbeta, workspace,
+                                        workspace_bytes);
+    if (st != OCD_OK) return st;
+    if (!best) return OCD_EINVAL;
+    if (pb->W == 0) {
+        *best = heuristic_plan(pb, lambda, true, false);
+        return OCD_OK;
+    }
+    repeats = std::max(1, std::min(repeats, 100));
+    std::vector<ocd_plan> cands;
+    for (int L : {4, 8, 16, 32}) {
+        const int cap = 512 / L;
+        std::vector<int> vs;
+        for (int v = cap; v >= 1 && v >= cap / 16; v /= 2) vs.push_back(v);
+        if (pb->S > 1)
+            for (int m = pb->S; m <= cap && m <= 4 * pb->S; m += pb->S) vs.push_back(m);
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        for (int v : vs)
+            for (int x : {0, 1}) {
+                ocd_plan pl = {L, v, x, 0};
+                Params P;
+                int npl, threads;
+                size_t lds;
+                if (make_params(pb, pl, lambda, true, P, npl, threads, lds)) cands.push_back(pl);
+            }
+    }
+    if (cands.empty()) return OCD_EUNSUPPORTED;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return OCD_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OCD_EDEVICE; }
+    float best_ms = 1e30f;
+    ocd_plan best_pl = cands[0];
+    for (const ocd_plan &pl : cands) {
+        st = run_backward(pb, pl, H, y, lambda, z_hist, dllr, dlambda, dbeta, dy, workspace, stream);
+        if (st != OCD_OK) break;
+        (void)hipEventRecord(e0, stream);
+        for (int i = 0; i < repeats && st == OCD_OK; ++i)
+            st = run_backward(pb, pl, H, y, lambda, z_hist, dllr, dlambda, dbeta, dy, workspace,
+                              stream);
+        (void)hipEventRecord(e1, stream);
+        if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) { st = OCD_EDEVICE; break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best_pl = pl; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != OCD_OK) return st;
+    store_plan(plan_key(pb, false, true), best_pl, true);
+    store_plan(plan_key(pb, true, true), best_pl, true);
+    *best = best_pl;
+    return OCD_OK;
 }

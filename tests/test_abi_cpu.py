@@ -15,7 +15,11 @@ LIB = os.path.join(ROOT, "paper_1611_08779_amd", "libocd.so")
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        from paper_1611_08779_amd import build as b
+        import importlib.util
+        spec = importlib.util.spec_from_file_location(
+            "ocd_hip_build", os.path.join(ROOT, "paper_1611_08779_amd", "build.py"))
+        b = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(b)
         b.build()
     return ctypes.CDLL(LIB)
 
