@@ -5,13 +5,13 @@
 
 namespace ocd {
 
-template <int L, int NPL, bool F16, bool BOX>
+template <int L, int NPL, bool F16, bool BOX, int UC>
 __global__ __launch_bounds__(512) void k_forward(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem sm = carve(smem, P, blockDim.x / L, false);
     const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    forward_tile<L, NPL, F16, BOX>(P, sm, tile_of(P, bid));
+    forward_tile<L, NPL, F16, BOX, UC>(P, sm, tile_of(P, bid));
 }
 
 // Standalone preprocessing: one wavefront per (subcarrier, user) column.
@@ -44,10 +44,10 @@ __global__ __launch_bounds__(256) void k_preprocess(Params P, float *g, float *d
     }
 }
 
-template <int L, int NPL, bool F16, bool BOX>
-static hipError_t launch_fwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
+template <int L, int NPL, bool F16, bool BOX, int UC>
+static hipError_t launch_fwd_u(const Params &p, int threads, size_t lds, hipStream_t s)
 {
-    auto fn = k_forward<L, NPL, F16, BOX>;
+    auto fn = k_forward<L, NPL, F16, BOX, UC>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -55,6 +55,15 @@ static hipError_t launch_fwd_t(const Params &p, int threads, size_t lds, hipStre
     }
     hipLaunchKernelGGL(fn, dim3(p.nblocks), dim3(threads), lds, s, p);
     return hipGetLastError();
+}
+
+// Exactly 8 users with at most 8 entries per lane take the unrolled user loop.
+template <int L, int NPL, bool F16, bool BOX>
+static hipError_t launch_fwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
+{
+    if constexpr (NPL <= 8)
+        if (p.U == 8) return launch_fwd_u<L, NPL, F16, BOX, 8>(p, threads, lds, s);
+    return launch_fwd_u<L, NPL, F16, BOX, 0>(p, threads, lds, s);
 }
 
 template <int L, int NPL>

@@ -21,7 +21,13 @@ namespace ocd {
 // the LLRs.  Every thread of the workgroup must call it (it contains barriers);
 // threads of idle lane groups may return before the others finish, so a caller
 // that reuses the LDS for another tile must synchronise first.
-template <int L, int NPL, bool F16, bool BOX>
+//
+// UC > 0: U == UC and the user loop is unrolled: z stays in registers, every
+// LDS address of a coordinate update is a compile-time offset from one base (the
+// rows of H_w are L * NPL apart) and the straight-line sweep lets the compiler
+// read the next column while the current update computes; UC = 0: U is a
+// run-time bound.
+template <int L, int NPL, bool F16, bool BOX, int UC = 0>
 __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
 {
     const int U = P.U, Bpad = P.Bpad;
@@ -56,7 +62,28 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
         if (P.z_hist && active)
             for (int u = j; u < U; u += L) P.z_hist[((long)v * P.K + k) * U + u] = zv[u];
     };
-    if (U == 1 || NPL > 8) {
+    if constexpr (UC > 0) {
+        constexpr int BP = L * NPL;
+        float2 zr[UC];
+#pragma unroll
+        for (int u = 0; u < UC; ++u) zr[u] = make_float2(0.f, 0.f);
+        for (int k = 0; k < P.K; ++k) {
+            const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
+#pragma unroll
+            for (int u = 0; u < UC; ++u) {
+                float2 h[NPL];
+                load_column<L, NPL>(Hs + u * BP, j, h);
+                zr[u] = coordinate_update<L, NPL, BOX>(h, dpk[u], zr[u], beta, r);
+            }
+            if (P.z_hist) {
+#pragma unroll
+                for (int u = 0; u < UC; ++u) zv[u] = zr[u];
+                sweep_done(k);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UC; ++u) zv[u] = zr[u];   // for the outputs below
+    } else if (U == 1 || NPL > 8) {
         // a single user: every update reads the z it wrote the step before; with
         // more than 8 entries per lane a second operand buffer would cost more
         // occupancy than it hides latency
