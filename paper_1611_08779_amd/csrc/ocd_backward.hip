@@ -65,12 +65,12 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     // H_w chunk loads, then y, then the LDS stores of H (see forward_tile)
     const int chunks = t.nslots * U * (Bpad >> 1);
     float4 hbuf[STAGE_CHUNKS];
-    stage_h_load<F16>(P, t.w_first, chunks, 0, hbuf);
+    stage_h_load<F16>(P, t.w_first, t.nslots, chunks, 0, hbuf);
     float2 r[NPL];
     load_vector<L, NPL, F16>(P, P.y, t, grp, j, active, r);
-    stage_h_store(P, sm, chunks, 0, hbuf);
-    stage_h_copy<F16>(P, sm, t.w_first, chunks, STAGE_CHUNKS * (int)blockDim.x);
-    stage_preprocess(P, sm, t.w_first, t.nslots);
+    stage_h_store(P, sm, t.nslots, chunks, 0, hbuf);
+    stage_h_copy<F16>(P, sm, t.w_first, t.nslots, chunks, STAGE_CHUNKS * (int)blockDim.x);
+    stage_preprocess<L * NPL>(P, sm, t.w_first, t.nslots);
     clear_padding<L, NPL>(P, j, active, r);
     const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
     const float2 *dps = sm.dp + (size_t)slot * Kt * U;

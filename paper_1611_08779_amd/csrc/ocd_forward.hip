@@ -14,27 +14,30 @@ __global__ __launch_bounds__(512) void k_forward(Params P)
     forward_tile<L, NPL, F16, BOX, UC>(P, sm, tile_of(P, bid));
 }
 
-// Standalone preprocessing: one wavefront per (subcarrier, user) column.
+// Standalone preprocessing: a 16-lane group per (subcarrier, user) column, lane l
+// summing entries l, l + 16, ... and the same DPP tree as the fused staging, so
+// both paths give bit-identical g, d^-1 and p.
 template <bool F16>
 __global__ __launch_bounds__(256) void k_preprocess(Params P, float *g, float *dinv, float *pp)
 {
     const int Kt = P.per_sweep ? P.K : 1;
-    const long col = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (col >= (long)P.W * P.U) return;
+    const long col = (long)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+    const int l16 = threadIdx.x & 15;
+    const bool live = col < (long)P.W * P.U;
+    float acc = 0.f;
+    if (live) {
+        for (int b = l16; b < P.B; b += 16) {
+            float2 v;
+            load_chunk<F16, 1>(P.H, col * P.B + b, b, P.B, false, &v);
+            acc = fmaf(v.x, v.x, fmaf(v.y, v.y, acc));
+        }
+    }
+    acc = group_sum<16>(acc);
+    if (!live) return;
     const long w = col / P.U;
     const int u = (int)(col - w * P.U);
-    // same summation order as the fused staging (lane-strided, then wave_sum), so
-    // both paths give bit-identical g, d^-1 and p
-    float acc = 0.f;
-    for (int b = lane; b < P.B; b += 64) {
-        float2 v;
-        load_chunk<F16, 1>(P.H, col * P.B + b, b, P.B, false, &v);
-        acc = fmaf(v.x, v.x, fmaf(v.y, v.y, acc));
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) g[col] = acc;
-    for (int kt = lane; kt < Kt; kt += 64) {
+    if (l16 == 0) g[col] = acc;
+    for (int kt = l16; kt < Kt; kt += 16) {
         const float lam = P.lambda ? P.lambda[kt] : P.lam_default;
         const float den = acc + lam;
         const float di = den > 0.f ? 1.0f / den : 0.f;
@@ -106,10 +109,10 @@ hipError_t launch_preprocess(bool f16, const Params &p, float *g, float *dinv, f
 {
     const long cols = (long)p.W * p.U;
     if (cols == 0) return hipSuccess;
-    const int per_block = 4;
+    const int per_block = 16;   // 16-lane groups of a 256-thread block
     const dim3 grid((unsigned)((cols + per_block - 1) / per_block));
-    if (f16) hipLaunchKernelGGL(k_preprocess<true>, grid, dim3(64 * per_block), 0, s, p, g, dinv, pp);
-    else hipLaunchKernelGGL(k_preprocess<false>, grid, dim3(64 * per_block), 0, s, p, g, dinv, pp);
+    if (f16) hipLaunchKernelGGL(k_preprocess<true>, grid, dim3(256), 0, s, p, g, dinv, pp);
+    else hipLaunchKernelGGL(k_preprocess<false>, grid, dim3(256), 0, s, p, g, dinv, pp);
     return hipGetLastError();
 }
 

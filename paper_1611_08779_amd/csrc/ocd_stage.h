@@ -89,13 +89,31 @@ __device__ __forceinline__ Tile tile_of(const Params &P, int bid)
 // consecutive in [W][U][B]) and antennas 2 (c mod Bpad/2) and the next one.
 constexpr int STAGE_CHUNKS = 4;
 
+// Dense staging: rows of even length B = Bpad, aligned, and one subcarrier per
+// tile.  Then chunk c is complex entries 2c and 2c + 1 both of the tile's rows in
+// global memory and of the LDS slot, and needs no row/antenna arithmetic.
+__device__ __forceinline__ bool dense_stage(const Params &P, int nslots)
+{
+    return P.vec_ok && P.B == P.Bpad && nslots == 1;
+}
+
 template <bool F16>
-__device__ __forceinline__ void stage_h_load(const Params &P, int w_first, int total, int c0,
-                                             float4 (&buf)[STAGE_CHUNKS])
+__device__ __forceinline__ void stage_h_load(const Params &P, int w_first, int nslots, int total,
+                                             int c0, float4 (&buf)[STAGE_CHUNKS])
 {
     const int half = P.Bpad >> 1;
     const int sh = __ffs(half) - 1;   // Bpad is a power of two
     const long rbase = (long)w_first * P.U;
+    if (dense_stage(P, nslots)) {
+        const unsigned char *hb =
+            static_cast<const unsigned char *>(P.H) + (size_t)rbase * P.B * cbytes<F16>();
+#pragma unroll
+        for (int i = 0; i < STAGE_CHUNKS; ++i) {
+            const int c = c0 + i * (int)blockDim.x + (int)threadIdx.x;
+            buf[i] = load_pair_at<F16>(hb, c < total ? (unsigned)c * 2u * cbytes<F16>() : 0u);
+        }
+        return;
+    }
     if (P.vec_ok) {
         // B even: a chunk is wholly inside or wholly outside the row.  Out-of-range
         // chunks load a valid address and are replaced by zeros, so no load sits
@@ -131,9 +149,17 @@ __device__ __forceinline__ int slot_of_row(const Params &P, int row)
     return (int)fmaf((float)row, P.invU, 0.5f * P.invU);
 }
 
-__device__ __forceinline__ void stage_h_store(const Params &P, const Smem &sm, int total, int c0,
-                                              const float4 (&buf)[STAGE_CHUNKS])
+__device__ __forceinline__ void stage_h_store(const Params &P, const Smem &sm, int nslots,
+                                              int total, int c0, const float4 (&buf)[STAGE_CHUNKS])
 {
+    if (dense_stage(P, nslots)) {
+#pragma unroll
+        for (int i = 0; i < STAGE_CHUNKS; ++i) {
+            const int c = c0 + i * (int)blockDim.x + (int)threadIdx.x;
+            if (c < total) *reinterpret_cast<float4 *>(sm.H + 2 * c) = buf[i];
+        }
+        return;
+    }
     const int half = P.Bpad >> 1;
     const int sh = __ffs(half) - 1;
     const int gap = P.slot_stride - P.U * P.Bpad;   // padding between LDS slots
@@ -153,12 +179,12 @@ __device__ __forceinline__ void stage_h_store(const Params &P, const Smem &sm, i
 // Copies H_w of every touched subcarrier into LDS (all passes).
 template <bool F16>
 __device__ __forceinline__ void stage_h_copy(const Params &P, const Smem &sm, int w_first,
-                                             int total, int c0)
+                                             int nslots, int total, int c0)
 {
     for (; c0 < total; c0 += STAGE_CHUNKS * (int)blockDim.x) {
         float4 buf[STAGE_CHUNKS];
-        stage_h_load<F16>(P, w_first, total, c0, buf);
-        stage_h_store(P, sm, total, c0, buf);
+        stage_h_load<F16>(P, w_first, nslots, total, c0, buf);
+        stage_h_store(P, sm, nslots, total, c0, buf);
     }
 }
 
@@ -206,9 +232,12 @@ __device__ __forceinline__ void axis_llrs(float t, float c, float *dst)
 // precomputed values): g_u = ||h_u||^2, d_u^-1 = (g_u + lambda_k)^-1 (0 if that
 // is 1/0), p_u = d_u^-1 g_u.  Ends with a workgroup barrier, after which the
 // staged H_w is visible to every thread.
+// BP = L * NPL (= P.Bpad) is a compile-time constant, so the row reads unroll and
+// issue together.
+template <int BP>
 __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, int nslots)
 {
-    const int U = P.U, Bpad = P.Bpad;
+    const int U = P.U, Bpad = BP;
     const int Kt = P.per_sweep ? P.K : 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
     const int rows = nslots * U;
@@ -228,20 +257,29 @@ __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, i
         return;
     }
     __syncthreads();
-    for (int row = wave; row < rows; row += nwaves) {
-        const int slot = slot_of_row(P, row), u = row - slot * U;
-        const float2 *h = sm.H + (size_t)slot * P.slot_stride + (size_t)u * Bpad;
+    // a 16-lane group per row (one DPP row), rows dealt round-robin over the waves;
+    // lane l of the group sums entries l, l + 16, ... (k_preprocess sums the same way)
+    const int grp16 = lane >> 4, l16 = lane & 15;
+    for (int base = 0; base < rows; base += 4 * nwaves) {
+        const int row = base + wave + grp16 * nwaves;
+        const bool live = row < rows;
+        const int slot = live ? slot_of_row(P, row) : 0, u = live ? row - slot * U : 0;
         float acc = 0.f;
-        for (int b = lane; b < Bpad; b += 64) acc = fmaf(h[b].x, h[b].x, fmaf(h[b].y, h[b].y, acc));
-        acc = wave_sum(acc);
-        if (lane == 0) {
+        if (live) {
+            const float2 *h = sm.H + (size_t)slot * P.slot_stride + (size_t)u * Bpad;
+#pragma unroll
+            for (int b = l16; b < BP; b += 16) acc = fmaf(h[b].x, h[b].x, fmaf(h[b].y, h[b].y, acc));
+        }
+        acc = group_sum<16>(acc);
+        if (!live) continue;
+        if (l16 == 0) {
             sm.g[row] = acc;
             // p of the last sweep, computed as for sm.dp below
             const float den = acc + lamK;
             const float di = den > 0.f ? 1.0f / den : 0.f;
             sm.lc[row] = llr_coef(P, acc, di * acc, lamK);
         }
-        for (int kt = lane; kt < Kt; kt += 64) {
+        for (int kt = l16; kt < Kt; kt += 16) {
             const float lam = P.lambda ? P.lambda[kt] : P.lam_default;
             const float den = acc + lam;
             const float di = den > 0.f ? 1.0f / den : 0.f;
@@ -249,14 +287,6 @@ __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, i
         }
     }
     __syncthreads();
-}
-
-// H_w copy and preprocessing in one go (for callers with nothing to overlap).
-template <bool F16>
-__device__ void stage_subcarriers(const Params &P, const Smem &sm, int w_first, int nslots)
-{
-    stage_h_copy<F16>(P, sm, w_first, nslots * P.U * (P.Bpad >> 1), 0);
-    stage_preprocess(P, sm, w_first, nslots);
 }
 
 // Loads this lane's NPL receive entries of vector v.  On the vector path the

@@ -43,12 +43,12 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     // wait only for the H chunks.
     const int chunks = tile.nslots * U * (Bpad >> 1);
     float4 hbuf[STAGE_CHUNKS];
-    stage_h_load<F16>(P, tile.w_first, chunks, 0, hbuf);
+    stage_h_load<F16>(P, tile.w_first, tile.nslots, chunks, 0, hbuf);
     float2 r[NPL];
     load_vector<L, NPL, F16>(P, P.y, tile, grp, j, active, r);
-    stage_h_store(P, sm, chunks, 0, hbuf);
-    stage_h_copy<F16>(P, sm, tile.w_first, chunks, STAGE_CHUNKS * (int)blockDim.x);
-    stage_preprocess(P, sm, tile.w_first, tile.nslots);
+    stage_h_store(P, sm, tile.nslots, chunks, 0, hbuf);
+    stage_h_copy<F16>(P, sm, tile.w_first, tile.nslots, chunks, STAGE_CHUNKS * (int)blockDim.x);
+    stage_preprocess<L * NPL>(P, sm, tile.w_first, tile.nslots);
     clear_padding<L, NPL>(P, j, active, r);
 
     const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
