@@ -572,13 +572,15 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     wsb = torch.empty(ocd.ocd_backward_workspace_bytes(pb5), dtype=torch.uint8, device=dev)
     bits = wl["bits"].float()
     inv_n = 1.0 / bits.numel()
+    nbits_s = bits * -inv_n          # -bit / N, fixed labels
     z5 = torch.empty(W5, S5, U5, dtype=torch.complex64, device=dev)
-    ocd.ocd_autotune(pb5, wl["H"], wl["y"], z5, L5, repeats=3)
+    plan_f = ocd.ocd_autotune(pb5, wl["H"], wl["y"], z5, L5, repeats=3)
     del z5
 
     def fwd_bwd():
         ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
-        dllr = (torch.sigmoid(L5) - bits) * inv_n
+        # gradient of the mean BCE with logits: (sigmoid(L) - bit) / N, two elementwise ops
+        dllr = torch.add(nbits_s, torch.sigmoid(L5), alpha=inv_n)
         ocd.ocd_detect_backward(pb5, wl["H"], wl["y"], lam, zh, dllr, dlam, dbeta, dy, wsb)
 
     def fwd_only():
@@ -587,7 +589,8 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     fwd_only_once = lambda: ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
     fwd_only_once()
     dllr0 = (torch.sigmoid(L5) - bits) * inv_n
-    ocd.ocd_autotune_backward(pb5, wl["H"], wl["y"], lam, zh, dllr0, dlam, dbeta, dy, wsb, repeats=3)
+    plan_b = ocd.ocd_autotune_backward(pb5, wl["H"], wl["y"], lam, zh, dllr0, dlam, dbeta, dy, wsb,
+                                       repeats=3)
     del dllr0
     tfb, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd] * 8), 400, 16)
     tf, _ = time_graph(torch, GraphedSteps(torch, [fwd_only] * 8), 400, 16)
@@ -598,6 +601,7 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
         "workload": "B=128 U=16, 2048 subcarriers x 4 symbols, 16-QAM, K=4, HYBRID (learnable "
                     "lambda_k, beta), BCE of LLRs, 10 dB",
         "fwd_tflops": fl * W5 * S5 / tf / 1e12,
+        "plan_forward": plan_f.as_dict(), "plan_backward": plan_b.as_dict(),
     }
     return forms
 

@@ -117,9 +117,12 @@ size_t ocd_backward_workspace_bytes(const ocd_problem *pb);
 
 /* Adjoint of ocd_detect with respect to the per-sweep regularisers, the box
  * half-width and the receive vectors (H is not differentiated).  The K sweeps
- * are reversed one coordinate update at a time; the residual before every
- * update is recovered from the one after it (r_pre = r_post + h_u Delta) rather
- * than stored, so only z_hist is kept from the forward pass.
+ * are reversed one coordinate update at a time.  Only z_hist is kept from the
+ * forward pass, and the residual is never rebuilt: the update computes
+ * c = d_u^-1 (h_u^H r + g_u z_u), so dc/dlambda_k = -d_u^-1 c, and c equals the
+ * stored z_u' wherever it was not clipped (where it was, its adjoint is zero).
+ *   y           the receive vectors of the forward call; not read (the adjoint
+ *               depends on y only through z_hist), but must be a valid pointer
  *   z_hist      device [W][S][K][U], written by ocd_detect with the same arguments
  *   dllr        device [W][S][U][Q], dLoss/dLLR
  *   dlambda     device [K]  dLoss/dlambda_k (overwritten)
@@ -127,8 +130,10 @@ size_t ocd_backward_workspace_bytes(const ocd_problem *pb);
  *   dy          device [W][S][B] complex FP32, dLoss/dRe y + j dLoss/dIm y (may be NULL)
  *   workspace   device, >= ocd_backward_workspace_bytes(pb) bytes, 16-byte aligned
  * dlambda and dbeta are reduced in a fixed order: repeated calls give identical bits.
- * Subgradient conventions: |c| <= beta counts as unclipped; the max-log minimisers
- * are the first ones found. */
+ * Subgradient conventions: a component of z_u' strictly inside (-beta, beta) is
+ * unclipped and one at +-beta clipped (c exactly at +-beta, where the projection's
+ * derivative is one-sided, has measure zero); the max-log minimisers are the first
+ * ones found. */
 ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void *y,
                                const float *lambda, const float *z_hist, const float *dllr,
                                float *dlambda, float *dbeta, float *dy,

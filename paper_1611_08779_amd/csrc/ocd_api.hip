@@ -158,7 +158,7 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
         lds = 0;
         return true;
     }
-    lds = lds_bytes(P, threads / L, backward);
+    lds = lds_bytes(P, threads / L, backward, threads / 64);
     return lds <= (size_t)lds_limit_bytes();
 }
 

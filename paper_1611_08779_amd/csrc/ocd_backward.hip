@@ -1,17 +1,20 @@
 // ocd_backward.hip -- adjoint of Algorithm 1 plus the soft output.
 //
-// Per vector the kernel rebuilds the final residual r^(K) = y - H z^(K) from the
-// stored history, seeds dLoss/dz from dLoss/dLLR through the max-log LLR, and
-// then walks the K*U coordinate updates backwards.  For the update (k, u):
-//   forward   c = d^-1 h^H r_pre + p z_old,  z_new = proj(c),
-//             r_post = r_pre - h (z_new - z_old)
-//   reverse   r_pre  = r_post + h (z_new - z_old)           (recomputed, not stored)
-//             Delta_bar = -h^H r_bar,  t = z_bar + Delta_bar
-//             c_bar = t on unclipped parts, 0 on clipped ones (those add sign(c) t to beta_bar)
-//             lambda_bar_k += -d^-2 Re(conj(h^H r_pre) c_bar) - g d^-2 Re(conj(z_old) c_bar)
-//             z_bar = -Delta_bar + p c_bar,  r_bar += h d^-1 c_bar
-// y_bar is r_bar after the first update.  Each update costs three lane-local
-// complex dot/axpy passes plus one 4-float all-reduce, about twice the forward.
+// The forward update (k, u) computes c = d^-1 (h^H r + g z_old) with
+// d^-1 = (g + lambda_k)^-1, so dc/dlambda_k = -d^-1 c, and z_new = proj(c).
+// Where a component of c is not clipped it equals that component of z_new, and
+// where it is clipped its adjoint is zero; so the adjoint of the update needs
+// only z_new (stored per sweep in z_hist), never the residual r:
+//   Delta_bar = -h^H r_bar,  t = z_bar + Delta_bar
+//   c_bar = t on unclipped parts, 0 on clipped ones (those add sign(z_new) t to beta_bar)
+//   lambda_bar_k += -d^-1 Re(conj(z_new) c_bar)
+//   z_bar = -Delta_bar + p c_bar,  r_bar += h d^-1 c_bar
+// walked backwards over k = K..1, u = U..1, after seeding z_bar from dLoss/dLLR
+// through the max-log LLR (and lambda_bar_K through mu and rho).  y_bar is r_bar
+// at the end; y itself is not read.  Each update costs one lane-local inner
+// product, one 2-float all-reduce and one axpy: the work of a forward update.
+// A component of z_new equal to +-beta counts as clipped (c exactly at +-beta,
+// where the projection's derivative is one-sided, has measure zero).
 // Per-sweep and box partial sums go to a per-workgroup slot of the workspace
 // and are reduced in a fixed order by k_reduce_partials.
 #include "ocd_stage.h"
@@ -62,33 +65,23 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     const int v = t.vbase + (active ? grp : 0);
     const int slot = slot_of_group(P, t, active ? grp : 0);
 
-    // H_w chunk loads, then y, then the LDS stores of H (see forward_tile)
+    // H_w staged as in forward_tile (the adjoint never needs the receive vector)
     const int chunks = t.nslots * U * (Bpad >> 1);
     float4 hbuf[STAGE_CHUNKS];
     stage_h_load<F16>(P, t.w_first, t.nslots, chunks, 0, hbuf);
-    float2 r[NPL];
-    load_vector<L, NPL, F16>(P, P.y, t, grp, j, active, r);
     stage_h_store(P, sm, t.nslots, chunks, 0, hbuf);
     stage_h_copy<F16>(P, sm, t.w_first, t.nslots, chunks, STAGE_CHUNKS * (int)blockDim.x);
     stage_preprocess<L * NPL>(P, sm, t.w_first, t.nslots);
-    clear_padding<L, NPL>(P, j, active, r);
     const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
     const float2 *dps = sm.dp + (size_t)slot * Kt * U;
     const float *gs = sm.g + (size_t)slot * U;
     const int zr = zrow_of(P, grp);
-    float2 *zv = sm.z + (size_t)zr * U;
-    float2 *zp = sm.zprev + (size_t)zr * U;
-    float2 *zb = sm.zbar + (size_t)zr * U;
+    float2 *zv = sm.z + (size_t)zr * U;      // z^(k) of the sweep being reversed
+    float2 *zb = sm.zbar + (size_t)zr * U;   // dLoss/dz
     const float2 *zh = P.zh_in + (long)v * K * U;
 
-    // z^(K) and the final residual r^(K) = y - H z^(K)
     for (int u = 0; u < U; ++u)
         zv[u] = active ? zh[(size_t)(K - 1) * U + u] : make_float2(0.f, 0.f);
-    for (int u = 0; u < U; ++u) {
-        float2 h[NPL];
-        load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
-        axpy_sub<NPL>(h, zv[u], r);
-    }
 
     // soft-output adjoint, one owner lane per user
     const float lamK = P.lambda ? P.lambda[K - 1] : P.lam_default;
@@ -125,55 +118,71 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     float beta_bar = 0.f;
     float *part_out = P.partials + (size_t)bid * (K + 1);
 
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    // z^(k) rows: lane j owns users j, j + L, ...; with U <= ZPL * L the row of the
+    // next sweep is loaded into registers while the current sweep computes
+    constexpr int ZPL = 4;
+    const bool zpre = U <= ZPL * L;
+    float2 znext[ZPL];
+    auto fetch_row = [&](int k) {
+#pragma unroll
+        for (int i = 0; i < ZPL; ++i) {
+            const int u = j + i * L;
+            const bool ok = active && u < U;
+            znext[i] = zh[ok ? (size_t)k * U + u : 0];   // a valid address either way
+            if (!ok) znext[i] = make_float2(0.f, 0.f);
+        }
+    };
+    if (zpre && K >= 2) fetch_row(K - 2);
+    __syncthreads();   // z_bar rows of every group written (groups never span waves,
+                       // so later row updates need only the wave's own LDS order)
     for (int k = K - 1; k >= 0; --k) {
-        for (int u = j; u < U; u += L)
-            zp[u] = (k > 0 && active) ? zh[(size_t)(k - 1) * U + u] : make_float2(0.f, 0.f);
-        __syncthreads();   // z_prev and z_bar rows written by their owner lanes
+        if (k < K - 1) {
+            if (zpre) {
+#pragma unroll
+                for (int i = 0; i < ZPL; ++i)
+                    if (j + i * L < U) zv[j + i * L] = znext[i];
+                if (k >= 1) fetch_row(k - 1);
+            } else {
+                for (int u = j; u < U; u += L)
+                    zv[u] = active ? zh[(size_t)k * U + u] : make_float2(0.f, 0.f);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();   // z^(k) row written by its owner lanes
         const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
         float lam_bar = (k == K - 1) ? lamK_bar : 0.f;
         for (int u = U - 1; u >= 0; --u) {
             float2 h[NPL];
             load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
-            const float2 znew = zv[u], zold = zp[u];
-            axpy_add<NPL>(h, make_float2(znew.x - zold.x, znew.y - zold.y), r);   // r_pre
-            float2 ip = partial_inner<NPL>(h, r);
-            float2 hb = partial_inner<NPL>(h, rb);
-            ip.x = group_sum<L>(ip.x);
-            ip.y = group_sum<L>(ip.y);
+            float2 hb = partial_inner<NPL, 2>(h, rb);
             hb.x = group_sum<L>(hb.x);
             hb.y = group_sum<L>(hb.y);
-            const float2 dp = dpk[u];
-            const float cr = fmaf(dp.x, ip.x, dp.y * zold.x);
-            const float ci = fmaf(dp.x, ip.y, dp.y * zold.y);
-            const float2 zbu = zb[u];
+            const float2 dp = dpk[u], zn = zv[u], zbu = zb[u];
             const float tr = zbu.x - hb.x, ti = zbu.y - hb.y;   // z_bar + Delta_bar
             float cbr = tr, cbi = ti;
             if constexpr (BOX) {
-                if (fabsf(cr) > beta) { beta_bar += cr > 0.f ? tr : -tr; cbr = 0.f; }
-                if (fabsf(ci) > beta) { beta_bar += ci > 0.f ? ti : -ti; cbi = 0.f; }
+                if (!(fabsf(zn.x) < beta)) { beta_bar += zn.x > 0.f ? tr : -tr; cbr = 0.f; }
+                if (!(fabsf(zn.y) < beta)) { beta_bar += zn.y > 0.f ? ti : -ti; cbi = 0.f; }
             }
-            const float d2 = dp.x * dp.x;
-            lam_bar = fmaf(-d2, fmaf(ip.x, cbr, ip.y * cbi), lam_bar);
-            lam_bar = fmaf(-gs[u] * d2, fmaf(zold.x, cbr, zold.y * cbi), lam_bar);
+            lam_bar = fmaf(-dp.x, fmaf(zn.x, cbr, zn.y * cbi), lam_bar);
             zb[u] = make_float2(hb.x + dp.y * cbr, hb.y + dp.y * cbi);   // -Delta_bar + p c_bar
-            zv[u] = zold;
             axpy_add<NPL>(h, make_float2(dp.x * cbr, dp.x * cbi), rb);
         }
-        if (j == 0) sm.part[grp] = active ? lam_bar : 0.f;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float s = 0.f;
-            for (int g = 0; g < vpb_cap; ++g) s += sm.part[g];
-            part_out[k] = s;
-        }
-        __syncthreads();
+        // per-wave partial of sweep k, parked in LDS until the end
+        const float ws = wave_sum(active && j == 0 ? lam_bar : 0.f);
+        if ((threadIdx.x & 63) == 0) sm.part[k * nwaves + wave] = ws;
+        __builtin_amdgcn_wave_barrier();
     }
-    if (j == 0) sm.part[grp] = active ? beta_bar : 0.f;
+    {
+        const float ws = wave_sum(active && j == 0 ? beta_bar : 0.f);
+        if ((threadIdx.x & 63) == 0) sm.part[K * nwaves + wave] = ws;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float s = 0.f;
-        for (int g = 0; g < vpb_cap; ++g) s += sm.part[g];
-        part_out[K] = s;
+    // the workgroup's partials: waves summed in order (fixed order, reproducible)
+    for (int e = threadIdx.x; e <= K; e += blockDim.x) {
+        float sum = 0.f;
+        for (int w = 0; w < nwaves; ++w) sum += sm.part[e * nwaves + w];
+        part_out[e] = sum;
     }
     if (active && P.dy) {
 #pragma unroll

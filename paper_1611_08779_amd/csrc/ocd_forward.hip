@@ -60,12 +60,14 @@ static hipError_t launch_fwd_u(const Params &p, int threads, size_t lds, hipStre
     return hipGetLastError();
 }
 
-// Exactly 8 users with at most 8 entries per lane take the unrolled user loop.
+// Exactly 8 or 16 users with at most 8 entries per lane take the unrolled user loop.
 template <int L, int NPL, bool F16, bool BOX>
 static hipError_t launch_fwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
 {
-    if constexpr (NPL <= 8)
+    if constexpr (NPL <= 8) {
         if (p.U == 8) return launch_fwd_u<L, NPL, F16, BOX, 8>(p, threads, lds, s);
+        if (p.U == 16) return launch_fwd_u<L, NPL, F16, BOX, 16>(p, threads, lds, s);
+    }
     return launch_fwd_u<L, NPL, F16, BOX, 0>(p, threads, lds, s);
 }
 

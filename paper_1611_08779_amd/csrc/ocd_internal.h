@@ -43,7 +43,7 @@ struct Params {
 };
 
 // Bytes of dynamic LDS a launch of this shape needs.
-inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward)
+inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward, int nwaves = 0)
 {
     const int Kt = p.per_sweep ? p.K : 1;
     size_t b = 0;
@@ -54,9 +54,8 @@ inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward)
     b += (size_t)p.maxslots * p.U * 8;               // soft-output coefficients
     b += (size_t)(p.vpb + 1) * p.U * 8;              // z per vector (+ idle groups' row)
     if (backward) {
-        b += (size_t)(p.vpb + 1) * p.U * 8;          // z^(k-1) row per vector
         b += (size_t)(p.vpb + 1) * p.U * 8;          // z_bar per vector
-        b += (size_t)vpb_cap * 4;                    // per-group partials
+        b += (size_t)(p.K + 1) * (size_t)nwaves * 4; // per-wave partials of every sweep
     }
     return b;
 }

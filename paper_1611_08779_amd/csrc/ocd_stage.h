@@ -13,9 +13,8 @@ struct Smem {
     float2 *dp;    // [maxslots][Kt][U]: (d_u^-1, p_u)
     float2 *lc;    // [maxslots][U]: soft-output coefficients (see llr_coef)
     float2 *z;     // [vpb + 1][U]: current z of each vector; idle groups share the last row
-    float2 *zprev; // [vpb + 1][U]: adjoint only, z^(k-1) of the sweep being reversed
     float2 *zbar;  // [vpb + 1][U]: adjoint only, dLoss/dz
-    float *part;   // [vpb_cap]: adjoint only, per-group partial sums
+    float *part;   // [(K + 1) * waves]: adjoint only, per-wave partial sums of every sweep
 };
 
 // Row of the per-vector LDS arrays used by lane group grp.
@@ -39,11 +38,9 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const Params &P, int 
     const size_t zrows = (size_t)(P.vpb + 1) * P.U * 8;
     s.z = reinterpret_cast<float2 *>(smem + off);
     off += zrows;
-    s.zprev = s.zbar = nullptr;
+    s.zbar = nullptr;
     s.part = nullptr;
     if (backward) {
-        s.zprev = reinterpret_cast<float2 *>(smem + off);
-        off += zrows;
         s.zbar = reinterpret_cast<float2 *>(smem + off);
         off += zrows;
         s.part = reinterpret_cast<float *>(smem + off);
