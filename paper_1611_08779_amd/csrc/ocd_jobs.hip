@@ -52,6 +52,12 @@ constexpr size_t HEADER_BYTES = 256;
 //   persistent = 1: a fixed grid; each workgroup claims its next tile from the
 //                   queue head while it works on the current one.  Every
 //                   workgroup stops when the queue is exhausted.
+template <int L, int UC, bool F16, bool BOX>
+__device__ __forceinline__ void job_tile(const Params &P, unsigned char *smem, const Tile &t)
+{
+    forward_tile<L, JOB_NPL, F16, BOX, UC, false>(P, carve(smem, P, JOB_THREADS / L, false), t);
+}
+
 template <bool F16, bool BOX>
 __global__ __launch_bounds__(JOB_THREADS, 4) void k_jobs(const JobDesc *__restrict__ jobs,
                                                       const TileDesc *__restrict__ tiles,
@@ -81,11 +87,18 @@ __global__ __launch_bounds__(JOB_THREADS, 4) void k_jobs(const JobDesc *__restri
         t.nvb = __builtin_amdgcn_readfirstlane(td.nvb);
         t.w_first = t.vbase / P.S;
         t.nslots = (t.vbase + t.nvb - 1) / P.S - t.w_first + 1;
-        switch (jd.L) {
-        case 4: forward_tile<4, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 4, false), t); break;
-        case 8: forward_tile<8, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 8, false), t); break;
-        case 16: forward_tile<16, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 16, false), t); break;
-        default: forward_tile<32, JOB_NPL, F16, BOX>(P, carve(smem, P, JOB_THREADS / 32, false), t); break;
+        // 8 users unrolled as in the one-problem kernel (16 would not fit the
+        // register budget of four 512-thread workgroups per CU)
+        const int uc = P.U == 8 ? 8 : 0;
+        switch (jd.L * 100 + uc) {
+        case 400: job_tile<4, 0, F16, BOX>(P, smem, t); break;
+        case 408: job_tile<4, 8, F16, BOX>(P, smem, t); break;
+        case 800: job_tile<8, 0, F16, BOX>(P, smem, t); break;
+        case 808: job_tile<8, 8, F16, BOX>(P, smem, t); break;
+        case 1600: job_tile<16, 0, F16, BOX>(P, smem, t); break;
+        case 1608: job_tile<16, 8, F16, BOX>(P, smem, t); break;
+        case 3208: job_tile<32, 8, F16, BOX>(P, smem, t); break;
+        default: job_tile<32, 0, F16, BOX>(P, smem, t); break;
         }
         if (!persistent) break;
         __syncthreads();   // this tile is done with LDS (and with s_tile)

@@ -27,7 +27,9 @@ namespace ocd {
 // rows of H_w are L * NPL apart) and the straight-line sweep lets the compiler
 // read the next column while the current update computes; UC = 0: U is a
 // run-time bound.
-template <int L, int NPL, bool F16, bool BOX, int UC = 0>
+// PIPE: with a run-time U, read the next update's operands while the current
+// one computes (a second operand buffer); off where registers are scarce.
+template <int L, int NPL, bool F16, bool BOX, int UC = 0, bool PIPE = true>
 __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
 {
     const int U = P.U, Bpad = P.Bpad;
@@ -83,7 +85,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
         }
 #pragma unroll
         for (int u = 0; u < UC; ++u) zv[u] = zr[u];   // for the outputs below
-    } else if (U == 1 || NPL > 8) {
+    } else if (!PIPE || U == 1 || NPL > 8) {
         // a single user: every update reads the z it wrote the step before; with
         // more than 8 entries per lane a second operand buffer would cost more
         // occupancy than it hides latency
