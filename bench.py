@@ -269,7 +269,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--slots", type=int, default=34, help="distinct config slots cycled (31 MB each)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--main-only", action="store_true",
                     help="only the headline workload (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -367,9 +367,12 @@ def main():
                          np.max(np.abs(Lo).reshape(-1, U * Q), axis=1)))
     ber = float(torch.mean(((outs[0][1] > 0).to(torch.uint8) != slots[0]["bits"]).float()).item())
 
-    fwd_kernel = "ocd::k_forward<%d, %d, false, false>" % (plan.lanes_per_vector,
-                                                          max(2, 1 << math.ceil(math.log2(
-                                                              max(2, math.ceil(B / plan.lanes_per_vector))))))
+    npl = max(2, 1 << math.ceil(math.log2(max(2, math.ceil(B / plan.lanes_per_vector)))))
+    if plan.channel_in_registers:
+        fwd_kernel = "ocd::k_forward_reg<%d, %d, 8, false, false>" % (plan.lanes_per_vector, npl)
+    else:
+        uc = U if (U in (8, 16) and npl <= 8) else 0
+        fwd_kernel = "ocd::k_forward<%d, %d, false, false, %d>" % (plan.lanes_per_vector, npl, uc)
     traffic = read_traffic(TRAFFIC_TAG)
     result = {
         "metric": "detected Gb/s & % HBM peak (B=128,U=8,64QAM,K=3); fwd+bwd vectors/s",
