@@ -117,6 +117,28 @@ def test_backward_workspace_size_and_null_checks(lib):
     assert lib.ocd_detect_backward(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, 16, None) == -1
 
 
+def test_backward_autotune_rejects_bad_arguments(lib):
+    pb = Problem(**_good())
+    lib.ocd_backward_workspace_bytes.restype = ctypes.c_size_t
+    lib.ocd_backward_workspace_bytes.argtypes = [ctypes.POINTER(Problem)]
+    n = lib.ocd_backward_workspace_bytes(ctypes.byref(pb))
+    lib.ocd_autotune_backward.restype = ctypes.c_int
+    lib.ocd_autotune_backward.argtypes = ([ctypes.POINTER(Problem)] + [ctypes.c_void_p] * 8 +
+                                          [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p])
+    d = ctypes.c_void_p(0x1000)
+    best = ctypes.create_string_buffer(16)
+    # no place for the plan
+    assert lib.ocd_autotune_backward(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, n, 1, None,
+                                     None) == -1
+    # missing dbeta
+    assert lib.ocd_autotune_backward(ctypes.byref(pb), d, d, None, d, d, d, None, d, d, n, 1, best,
+                                     None) == -1
+    # workspace too small
+    assert lib.ocd_autotune_backward(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, 16, 1, best,
+                                     None) == -1
+
+
 def test_jobs_rejects_null_arguments(lib):
     lib.ocd_detect_jobs.restype = ctypes.c_int
     lib.ocd_detect_jobs.argtypes = [ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_void_p,

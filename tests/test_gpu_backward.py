@@ -114,7 +114,9 @@ def test_adjoint_is_bitwise_reproducible(ocd):
 
 
 @pytest.mark.parametrize("case", [(33, 5, 7, 3, 6, 2, "box"), (256, 32, 4, 14, 2, 3, "hybrid"),
-                                  (16, 4, 3, 1, 4, 9, "mmse")])
+                                  (16, 4, 3, 1, 4, 9, "mmse"),
+                                  # S = 1: z_hist from the channel-in-registers forward plan
+                                  (128, 8, 20, 1, 6, 3, "hybrid")])
 def test_adjoint_edge_shapes(ocd, case):
     B, U, W, S, Q, K, mode = case
     c = _case(ocd, mode, B, U, W, S, Q, K, 8.0, seed=3)
@@ -125,6 +127,28 @@ def test_adjoint_edge_shapes(ocd, case):
     assert rel(c["dy"], dy_o) <= GRAD_TOL
     if mode != "mmse" and dbeta_o != 0.0:
         assert abs(c["dbeta"] - dbeta_o) <= GRAD_TOL * abs(dbeta_o)
+
+
+def test_backward_autotuner_keeps_the_gradients(ocd):
+    """The adjoint autotuner returns an LDS plan; gradients with the tuned plan equal
+    those of the default plan up to the order of the partial sums."""
+    B, U, W, S, Q, K = 128, 16, 24, 4, 4, 4
+    c = _case(ocd, "hybrid", B, U, W, S, Q, K, seed=4)
+    pb = ocd.problem(B, U, W, S, Q, K, "hybrid", "f32", c["N0"], 1.0, c["beta"])
+    dlam = torch.empty(K, device="cuda")
+    dbeta = torch.empty(1, device="cuda")
+    dy = torch.empty(W, S, B, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+    plan = ocd.ocd_autotune_backward(pb, c["H"], c["y"], c["lam_t"], c["zh"], c["dllr_t"], dlam,
+                                     dbeta, dy, ws, repeats=1)
+    say("  tuned adjoint plan", plan.as_dict())
+    assert plan.lanes_per_vector in (4, 8, 16, 32) and plan.channel_in_registers == 0
+    d2 = ocd.backward(c["H"], c["y"], c["zh"], c["dllr_t"], K, Q, "hybrid", c["N0"], 1.0, c["beta"],
+                      lam=c["lam_t"])
+    torch.cuda.synchronize()
+    assert rel(host(d2[0]), c["dlam"]) <= 1e-5
+    assert rel(host(d2[2]), c["dy"]) <= 1e-6
+    assert abs(float(host(d2[1])[0]) - c["dbeta"]) <= 1e-5 * abs(c["dbeta"])
 
 
 def test_autograd_function_drives_the_kernels(ocd):
