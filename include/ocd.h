@@ -149,8 +149,8 @@ ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void 
  *                         once into LDS and shared by its vectors (the choice when many
  *                         symbols share H_w); 1: each vector's lane group keeps the
  *                         columns of its H_w in registers and nothing is staged (the
- *                         choice when few do).  1 needs U <= 8 and B <= 8 * lanes_per_vector,
- *                         and is forward-only. */
+ *                         choice when few do).  1 needs U <= 8 and
+ *                         B <= 8 * lanes_per_vector, and is forward-only. */
 typedef struct {
     int lanes_per_vector;
     int vectors_per_block;

@@ -125,6 +125,7 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
     if (L != 4 && L != 8 && L != 16 && L != 32) return false;
     npl = npl_for(pb->B, L);
     if (!npl) return false;
+    if (pl.channel_in_registers < 0 || pl.channel_in_registers > 1) return false;
     const bool reg = pl.channel_in_registers != 0;
     if (reg && (backward || (L != 16 && L != 32) || !reg_user_bound(pb->U, npl))) return false;
     const int cap = (reg ? 256 : 512) / L;
@@ -352,7 +353,8 @@ ocd_status run_forward(const ocd_problem *pb, const ocd_plan &pl, const void *H,
     }
     const bool f16 = pb->storage == OCD_STORE_F16;
     hipError_t e = pl.channel_in_registers
-                       ? launch_forward_reg(pl.lanes_per_vector, npl, P.reg_uc, f16, P, threads, stream)
+                       ? launch_forward_reg(pl.lanes_per_vector, npl, P.reg_uc, f16, P, threads,
+                                            stream)
                        : launch_forward(pl.lanes_per_vector, npl, f16, P, threads, lds, stream);
     return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
 }
@@ -426,7 +428,7 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
                 if (make_params(pb, pl, nullptr, false, P, npl, threads, lds)) cands.push_back(pl);
             }
     }
-    for (int L : {16, 32})   // channel columns in registers (no LDS)
+    for (int L : {16, 32}) {   // channel columns in registers (no LDS)
         for (int v = 256 / L; v >= 1 && v >= 64 / L; v /= 2) {
             ocd_plan pl = {L, v, 0, 1};
             Params P;
@@ -434,6 +436,7 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
             size_t lds;
             if (make_params(pb, pl, nullptr, false, P, npl, threads, lds)) cands.push_back(pl);
         }
+    }
     if (cands.empty()) return OCD_EUNSUPPORTED;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return OCD_EDEVICE;

@@ -114,6 +114,13 @@ __device__ __forceinline__ float4 load_pair_at(const unsigned char *base, unsign
     }
 }
 
+// FP16 storage: two consecutive complex entries as they are stored (two packed
+// half pairs), from a workgroup-uniform base plus a 32-bit byte offset.
+__device__ __forceinline__ u32x2_t load_pair_raw16(const unsigned char *base, unsigned off)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x2_t *>(base + off));
+}
+
 // Load `N` consecutive complex entries starting at element `e` of a row,
 // converting to FP32; entries at or beyond `limit` read as zero.  General
 // (branchy) path, used where vector loads are not allowed.

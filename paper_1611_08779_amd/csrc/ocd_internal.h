@@ -65,8 +65,8 @@ hipError_t launch_forward(int L, int NPL, bool f16, const Params &p, int threads
                           hipStream_t s);
 hipError_t launch_backward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
                            hipStream_t s);
-hipError_t launch_forward_reg(int L, int NPL, int UC, bool f16, const Params &p, int threads,
-                              hipStream_t s);
+hipError_t launch_forward_reg(int L, int NPL, int UC, bool f16, const Params &p,
+                              int threads, hipStream_t s);
 hipError_t launch_preprocess(bool f16, const Params &p, float *g, float *dinv, float *pp,
                              hipStream_t s);
 hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s);

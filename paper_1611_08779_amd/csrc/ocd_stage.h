@@ -368,8 +368,23 @@ __device__ __forceinline__ void fetch_operands(const float2 *Hs, int Bpad, const
 // two issue slots apart (their latency), and there is no final merge -- the
 // choice when several waves share a SIMD.  Two chains halve the dependency
 // depth for one merge per component -- the choice when few waves do.
-template <int NPL, int CHAINS = 1>
-__device__ __forceinline__ float2 partial_inner(const float2 *h, const float2 *r)
+// Channel entries are float2, or an IEEE half pair packed in 32 bits (FP16 storage
+// kept as is in registers): the FMAs below then take the half operands directly
+// (mixed-precision FMA, exact conversion, one rounding), with the same results as
+// converting first.
+__device__ __forceinline__ float hre(const float2 &v) { return v.x; }
+__device__ __forceinline__ float him(const float2 &v) { return v.y; }
+__device__ __forceinline__ float hre(const uint32_t &v)
+{
+    return __low2float(*reinterpret_cast<const __half2 *>(&v));
+}
+__device__ __forceinline__ float him(const uint32_t &v)
+{
+    return __high2float(*reinterpret_cast<const __half2 *>(&v));
+}
+
+template <int NPL, int CHAINS = 1, typename HT>
+__device__ __forceinline__ float2 partial_inner(const HT *h, const float2 *r)
 {
     static_assert(CHAINS == 1 || (CHAINS == 2 && NPL % 2 == 0), "one or two chains");
     float ar[CHAINS], ai[CHAINS];
@@ -378,10 +393,10 @@ __device__ __forceinline__ float2 partial_inner(const float2 *h, const float2 *r
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
         const int c = i % CHAINS;
-        ar[c] = fmaf(h[i].x, r[i].x, ar[c]);
-        ai[c] = fmaf(h[i].x, r[i].y, ai[c]);
-        ar[c] = fmaf(h[i].y, r[i].y, ar[c]);
-        ai[c] = fmaf(-h[i].y, r[i].x, ai[c]);
+        ar[c] = fmaf(hre(h[i]), r[i].x, ar[c]);
+        ai[c] = fmaf(hre(h[i]), r[i].y, ai[c]);
+        ar[c] = fmaf(him(h[i]), r[i].y, ar[c]);
+        ai[c] = fmaf(-him(h[i]), r[i].x, ai[c]);
     }
     if constexpr (CHAINS == 2) return make_float2(ar[0] + ar[1], ai[0] + ai[1]);
     return make_float2(ar[0], ai[0]);
@@ -416,8 +431,8 @@ __device__ __forceinline__ void axpy_add(const float2 *h, float2 a, float2 *r)
 // One coordinate update of Algorithm 1 for the lanes of a group:
 //   z_u' = proj(d_u^-1 h_u^H r + p_u z_u),  r <- r - h_u (z_u' - z_u).
 // h: this lane's part of column u; dp = (d_u^-1, p_u); zo = z_u.  Returns z_u'.
-template <int L, int NPL, bool BOX, int CHAINS = 1>
-__device__ __forceinline__ float2 coordinate_update(const float2 *h, float2 dp, float2 zo,
+template <int L, int NPL, bool BOX, int CHAINS = 1, typename HT>
+__device__ __forceinline__ float2 coordinate_update(const HT *h, float2 dp, float2 zo,
                                                     float beta, float2 *r)
 {
     float2 ip = partial_inner<NPL, CHAINS>(h, r);
@@ -435,10 +450,10 @@ __device__ __forceinline__ float2 coordinate_update(const float2 *h, float2 dp, 
     const float ndr = zo.x - cr, ndi = zo.y - ci, di = ci - zo.y;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
-        r[i].x = fmaf(h[i].x, ndr, r[i].x);
-        r[i].x = fmaf(h[i].y, di, r[i].x);
-        r[i].y = fmaf(h[i].x, ndi, r[i].y);
-        r[i].y = fmaf(h[i].y, ndr, r[i].y);
+        r[i].x = fmaf(hre(h[i]), ndr, r[i].x);
+        r[i].x = fmaf(him(h[i]), di, r[i].x);
+        r[i].y = fmaf(hre(h[i]), ndi, r[i].y);
+        r[i].y = fmaf(him(h[i]), ndr, r[i].y);
     }
     return make_float2(cr, ci);
 }

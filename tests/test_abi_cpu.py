@@ -147,3 +147,29 @@ def test_jobs_rejects_null_arguments(lib):
     pb = Problem(**_good())
     assert lib.ocd_detect_jobs(ctypes.byref(pb), None, None, None, None, 1, None, 0, 0, None) == -1
     assert lib.ocd_detect_jobs(ctypes.byref(pb), None, None, None, None, 0, None, 0, 0, None) == -1
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("lanes_per_vector", ctypes.c_int), ("vectors_per_block", ctypes.c_int),
+                ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int)]
+
+
+REG_PLANS = [
+    # (problem overrides, plan, expected status)
+    (dict(S=1), (16, 16, 0, 1), 0),
+    (dict(S=1), (32, 8, 0, 1), 0),
+    (dict(S=1), (32, 9, 0, 1), -2),          # more than 256 lanes per workgroup
+    (dict(S=1), (8, 32, 0, 1), -2),          # register plans take 16 or 32 lanes
+    (dict(S=1, U=9), (16, 16, 0, 1), -2),    # above the register user bound
+    (dict(S=1, B=300), (32, 8, 0, 1), -2),   # more than 8 entries per lane
+    (dict(S=1), (16, 32, 0, 2), -2),         # no such placement
+    (dict(S=1), (16, 16, 0, -1), -2),
+]
+
+
+@pytest.mark.parametrize("over,plan,status", REG_PLANS, ids=[str(p) for p in REG_PLANS])
+def test_register_plans_are_checked_on_the_host(lib, over, plan, status):
+    lib.ocd_set_plan.restype = ctypes.c_int
+    lib.ocd_set_plan.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Plan)]
+    pb = Problem(**{**_good(), **over})
+    assert lib.ocd_set_plan(ctypes.byref(pb), ctypes.byref(Plan(*plan))) == status

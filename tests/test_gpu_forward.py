@@ -162,13 +162,16 @@ def test_channel_in_registers_hybrid_and_preprocessed(ocd):
     assert llr_rel_err(host(L2), Lo) <= LLR_TOL_F32
 
 
-def test_channel_in_registers_fp16(ocd):
+@pytest.mark.parametrize("plan", [(32, 8, 0, 1), (16, 16, 0, 1), (16, 5, 0, 1), (32, 2, 0, 1)])
+def test_channel_in_registers_fp16(ocd, plan):
+    """FP16 storage kept packed in registers (mixed-precision FMAs): the same values as
+    the oracle on the FP16-rounded inputs, within the FP32 tolerance."""
     B, U, W, S, Q, K = 128, 8, 80, 1, 6, 3
     wl = synth.make_workload(B, U, W, S, Q, 15.0, seed=[12, 3])
     N0 = f32(wl["N0"])
     H16, y16 = to_f16_pairs(wl["H"]), to_f16_pairs(wl["y"])
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f16", N0)
-    ocd.ocd_set_plan(pb, ocd.Plan(32, 8, 0, 1))
+    ocd.ocd_set_plan(pb, ocd.Plan(*plan))
     z, L, _ = ocd.detect(dev(H16), dev(y16), K, Q, "mmse", N0, storage="f16")
     torch.cuda.synchronize()
     zo, Lo, _ = oracle_ref(from_f16_pairs(H16), from_f16_pairs(y16), K, Q, "mmse", N0)
