@@ -50,8 +50,9 @@ def _open(path):
     lib.oracle_grad.argtypes = common + [dp, dp, dp, dp, dp, dp]
     lib.oracle_ocd_trace.argtypes = [i, i, i, i, i, d, d, dp, d, dp, dp, dp]
     lib.oracle_constellation.argtypes = [i, dp, ctypes.POINTER(ctypes.c_uint)]
+    lib.oracle_mmse.argtypes = [i, i, i, i, i, d, d, dp, dp, dp, dp, dp, i]
     for f in ("oracle_ocd", "oracle_cd", "oracle_llr", "oracle_detect", "oracle_hard",
-              "oracle_grad", "oracle_ocd_trace", "oracle_constellation"):
+              "oracle_grad", "oracle_ocd_trace", "oracle_constellation", "oracle_mmse"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -217,3 +218,20 @@ def constellation(Q):
     if rc != n:
         raise ValueError("bad Q")
     return pts[0::2] + 1j * pts[1::2], lab
+
+
+def mmse(H, y, Q, N0=1.0, Es=1.0, threads=1):
+    """Explicit MMSE detection with the exact soft output (Sections II-B, II-E):
+    H [W,U,B], y [W,S,B] -> z [W,S,U], llr [W,S,U,Q], mu [W,U]."""
+    lib = _load()
+    H, y = _c128(H), _c128(y)
+    W, U, B = H.shape
+    S = y.shape[1]
+    z = np.zeros((W, S, U), np.complex128)
+    out = np.zeros((W, S, U, Q), np.float64)
+    mu = np.zeros((W, U), np.float64)
+    rc = lib.oracle_mmse(B, U, W, S, Q, float(N0), float(Es), _ptr(H), _ptr(y), _ptr(z),
+                         _ptr(out), _ptr(mu), _threads(threads))
+    if rc:
+        raise ValueError("oracle_mmse rejected its arguments")
+    return z, out, mu

@@ -43,6 +43,12 @@
  *   R6  A user with g_u + lambda_k = 0 gets dinv = 0 (never updated); a user
  *       with rho = 0 or mu = 0 gets LLR 0.
  *   R7  Ties: slicing and argmins take the first point in enumeration order.
+ *   R8  Explicit MMSE (Section II-B) writes A = G + N0 I for unit-energy
+ *       symbols; with symbol energy Es the regulariser is N0/Es, as in R1.
+ *   R9  Section II-E forms the exact gain from "row i of A^-1" and "column i
+ *       of G"; the oracle takes mu_i = sum_j [A^-1]_ij G_ji = [A^-1 G]_ii, the
+ *       reading under which mu_i is real and rho_i = mu_i/(1-mu_i) is the
+ *       post-equalisation SINR (pinned by the error-covariance test).
  *
  * Parity pins (tests/test_oracle_pins.py, all CPU):
  *   oracle_ocd   Alg. 1 form; equals oracle_cd (plain CD, eq:CDrule and
@@ -57,6 +63,11 @@
  *   oracle_hard  textbook MRC BER for U = 1 QPSK; transmitted bits at high SNR.
  *   oracle_grad  FP64 central finite differences of the oracle's own forward
  *                pass, away from kinks.
+ *   oracle_mmse  normal equations (G + lambda I) z = H^H y by matrix products;
+ *                a library linear solve; the K -> infinity limit of oracle_ocd;
+ *                U = 1 and orthogonal-column closed forms (where the LLRs equal
+ *                oracle_ocd's at K = 1); mu_i^2 Es / E|z_i - mu_i s_i|^2 =
+ *                rho_i from the explicit error covariance; 0 < mu_i < 1.
  */
 #include <complex.h>
 #include <math.h>
@@ -591,4 +602,129 @@ int oracle_grad(int B, int U, int W, int S, int K, int Q, int mode, double N0, d
     free(g); free(dinv); free(p); free(r); free(rbar); free(z); free(zbar);
     free(rpre); free(cval); free(zold); free(P.lambda);
     return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Explicit MMSE soft-output detection: Section II-B (the regularised Gram */
+/* matrix and its inverse) with the exact gain and SINR of Section II-E    */
+/* ---------------------------------------------------------------------- */
+
+/* Cholesky factor of a Hermitian positive definite n x n matrix (row-major):
+ * A = L L^H with L lower triangular and a real positive diagonal.  Returns -1
+ * when a pivot is not positive. */
+static int cholesky(int n, const cplx *A, cplx *Lf)
+{
+    for (int i = 0; i < n * n; ++i) Lf[i] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double d = creal(A[j * n + j]);
+        for (int k = 0; k < j; ++k) {
+            cplx l = Lf[j * n + k];
+            d -= creal(l) * creal(l) + cimag(l) * cimag(l);
+        }
+        if (!(d > 0.0)) return -1;
+        double ljj = sqrt(d);
+        Lf[j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            cplx s = A[i * n + j];
+            for (int k = 0; k < j; ++k) s -= Lf[i * n + k] * conj(Lf[j * n + k]);
+            Lf[i * n + j] = s / ljj;
+        }
+    }
+    return 0;
+}
+
+/* A^-1 column by column from the Cholesky factor: L w = e_j, then L^H x = w. */
+static void cholesky_inverse(int n, const cplx *Lf, cplx *Ainv)
+{
+    cplx *w = malloc(sizeof(cplx) * n);
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i < n; ++i) {
+            cplx s = (i == j) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) s -= Lf[i * n + k] * w[k];
+            w[i] = s / Lf[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            cplx s = w[i];
+            for (int k = i + 1; k < n; ++k) s -= conj(Lf[k * n + i]) * Ainv[k * n + j];
+            Ainv[i * n + j] = s / conj(Lf[i * n + i]);
+        }
+    }
+    free(w);
+}
+
+/* Explicit MMSE detection of every vector (reading R8 for the regulariser and
+ * R9 for the gain), then the max-log LLRs of eq:exactinversellr:
+ *   G = H^H H, A = G + (N0/Es) I, z = A^-1 (H^H y)               (Section II-B)
+ *   mu_i = row i of A^-1 times column i of G, rho_i = mu_i/(1-mu_i) (Section II-E)
+ *   L_{i,b} at x = z_i/(mu_i sqrt(Es)) against the unit-energy points (R4, R5).
+ * A user with mu_i <= 0 (an all-zero column) gets LLR 0 (R6).
+ * z [W][S][U] and llr [W][S][U][Q] may each be NULL; mu [W][U] may be NULL. */
+int oracle_mmse(int B, int U, int W, int S, int Q, double N0, double Es, const double *H,
+                const double *y, double *z, double *llr, double *mu_out, int threads)
+{
+    if (B < 1 || U < 1 || U > B || W < 0 || S < 0 || !(N0 > 0.0) || !(Es > 0.0)) return -1;
+    if (Q != 2 && Q != 4 && Q != 6) return -1;
+    cplx pts[64];
+    unsigned labels[64];
+    qam_points(Q, pts, labels);
+    const double lam = N0 / Es;
+    const cplx *Hc = (const cplx *)H, *yc = (const cplx *)y;
+    int failed = 0;
+#pragma omp parallel num_threads(threads > 0 ? threads : 1)
+    {
+        cplx *G = malloc(sizeof(cplx) * U * U), *A = malloc(sizeof(cplx) * U * U);
+        cplx *Lf = malloc(sizeof(cplx) * U * U), *Ainv = malloc(sizeof(cplx) * U * U);
+        cplx *mf = malloc(sizeof(cplx) * U);
+        double *mu = malloc(sizeof(double) * U), *rho = malloc(sizeof(double) * U);
+#pragma omp for schedule(static)
+        for (int w = 0; w < W; ++w) {
+            const cplx *Hw = Hc + (size_t)w * U * B;   /* column u at Hw + u*B */
+            for (int i = 0; i < U; ++i)
+                for (int j = 0; j < U; ++j) {
+                    cplx s = 0.0;
+                    for (int b = 0; b < B; ++b) s += conj(Hw[i * B + b]) * Hw[j * B + b];
+                    G[i * U + j] = s;
+                    A[i * U + j] = s + ((i == j) ? lam : 0.0);
+                }
+            if (cholesky(U, A, Lf)) {
+#pragma omp atomic write
+                failed = 1;
+                continue;
+            }
+            cholesky_inverse(U, Lf, Ainv);
+            for (int i = 0; i < U; ++i) {
+                cplx s = 0.0;
+                for (int j = 0; j < U; ++j) s += Ainv[i * U + j] * G[j * U + i];
+                mu[i] = creal(s);
+                rho[i] = mu[i] / (1.0 - mu[i]);
+                if (mu_out) mu_out[(size_t)w * U + i] = mu[i];
+            }
+            for (int s = 0; s < S; ++s) {
+                const size_t v = (size_t)w * S + s;
+                const cplx *yv = yc + v * B;
+                for (int i = 0; i < U; ++i) {
+                    cplx acc = 0.0;
+                    for (int b = 0; b < B; ++b) acc += conj(Hw[i * B + b]) * yv[b];
+                    mf[i] = acc;
+                }
+                for (int i = 0; i < U; ++i) {
+                    cplx zi = 0.0;
+                    for (int j = 0; j < U; ++j) zi += Ainv[i * U + j] * mf[j];
+                    if (z) {
+                        z[2 * (v * U + i)] = creal(zi);
+                        z[2 * (v * U + i) + 1] = cimag(zi);
+                    }
+                    if (!llr) continue;
+                    double *Lout = llr + (v * U + i) * Q;
+                    if (!(mu[i] > 0.0) || !(rho[i] > 0.0)) {
+                        for (int b = 0; b < Q; ++b) Lout[b] = 0.0;
+                        continue;
+                    }
+                    maxlog_one(Q, pts, labels, zi / (mu[i] * sqrt(Es)), rho[i], Lout, NULL, NULL);
+                }
+            }
+        }
+        free(G); free(A); free(Lf); free(Ainv); free(mf); free(mu); free(rho);
+    }
+    return failed ? -1 : 0;
 }

@@ -13,6 +13,7 @@ import subprocess
 import pytest
 
 import oracle
+import test_oracle_mmse_pins as mpins
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "ocd_oracle.c")
@@ -42,6 +43,20 @@ MUTANTS = [
     ("gradient Delta_bar sign", "cplx dbar = -hr;", "cplx dbar = hr;"),
     ("gradient drops the mu-path of lambda_K",
      "dlambda[K - 1] += dmu * (-g[u] / ((g[u] + lamK) * (g[u] + lamK)));", ""),
+    # explicit MMSE (Sections II-B, II-E)
+    ("MMSE regulariser ignores Es", "const double lam = N0 / Es;", "const double lam = N0;"),
+    ("Gram matrix without the conjugate", "s += conj(Hw[i * B + b]) * Hw[j * B + b];",
+     "s += Hw[i * B + b] * Hw[j * B + b];"),
+    ("matched filter without the conjugate", "acc += conj(Hw[i * B + b]) * yv[b];",
+     "acc += Hw[i * B + b] * yv[b];"),
+    ("Cholesky pivot drops the imaginary parts", "d -= creal(l) * creal(l) + cimag(l) * cimag(l);",
+     "d -= creal(l) * creal(l);"),
+    ("back substitution without conj(L)", "s -= conj(Lf[k * n + i]) * Ainv[k * n + j];",
+     "s -= Lf[k * n + i] * Ainv[k * n + j];"),
+    ("gain from column i of A^-1", "s += Ainv[i * U + j] * G[j * U + i];",
+     "s += Ainv[j * U + i] * G[j * U + i];"),
+    ("exact SINR taken as mu", "rho[i] = mu[i] / (1.0 - mu[i]);", "rho[i] = mu[i];"),
+    ("exact LLR point ignores the gain", "zi / (mu[i] * sqrt(Es))", "zi / sqrt(Es)"),
 ]
 
 BATTERY = [
@@ -64,6 +79,13 @@ BATTERY = [
     lambda: pins.test_symbol_energy_is_a_pure_scale("box"),
     lambda: pins.test_reference_gradient_matches_finite_differences("hybrid"),
     lambda: pins.test_reference_gradient_matches_finite_differences("box"),
+    lambda: mpins.test_mmse_satisfies_the_normal_equations(32, 8, 2.5),
+    lambda: mpins.test_mmse_matches_a_library_solve(),
+    lambda: mpins.test_mmse_is_the_limit_of_coordinate_descent(),
+    lambda: mpins.test_gain_and_sinr_are_those_of_the_error_covariance(3.0),
+    lambda: mpins.test_single_user_closed_form(4),
+    lambda: mpins.test_orthogonal_columns_equal_one_ocd_sweep(6),
+    lambda: mpins.test_high_snr_llr_signs_are_the_transmitted_bits(),
 ]
 
 
