@@ -14,7 +14,8 @@ on its stream.
 One JSON line goes to stdout; progress goes to stderr.  Besides the contract's
 fields it carries the roofline of the dominant kernel, the FP64 oracle timed on
 this host's cores, and the other forms: FP16 storage (speedup at equal BER),
-the S=1 variant (one H per vector, HBM-bound), 48 uneven jobs in one persistent
+the S=1 variant (one H per vector, HBM-bound), explicit MMSE detection (the
+detector OCD approximates, at paired bit errors), 48 uneven jobs in one persistent
 graph launch against one launch per job, and the forward+backward step of the
 differentiable form in vectors/s.
 
@@ -51,6 +52,16 @@ def algorithmic(B, U, S, K, Q, cbytes=8):
     multiplications per sweep in the paper's count) plus 4 B U / S for the
     preprocessing shared by S symbols; bytes = H share + y + LLRs + z."""
     flops = 16.0 * B * U * K + 4.0 * B * U / S
+    nbytes = cbytes * B * U / S + cbytes * B + 4.0 * U * Q + 8.0 * U
+    return flops, nbytes
+
+
+def algorithmic_mmse(B, U, S, Q, cbytes=8):
+    """Per-vector work of explicit MMSE detection (Sections II-B, II-E), in real
+    flops (8 per complex MAC): the Gram matrix's upper triangle U(U+1)/2 B and the
+    Gauss-Jordan inverse U^3 per subcarrier, shared by S symbols, then the matched
+    filter U B and z = A^-1 s, U^2, per vector.  Bytes as for OCD."""
+    flops = 8.0 * (U * (U + 1) / 2 * B + U ** 3) / S + 8.0 * (U * B + U * U)
     nbytes = cbytes * B * U / S + cbytes * B + 4.0 * U * Q + 8.0 * U
     return flops, nbytes
 
@@ -426,6 +437,71 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def mmse_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, errs_ocd, nbits):
+    """Explicit MMSE detection on the headline slots: a small plan search on the
+    first slot, then the same graph-replayed timing as the headline; bit errors
+    paired with OCD's (same channels and noise); and the S = 1 shape, where the
+    Gram matrix is no longer shared."""
+    log("form: explicit MMSE")
+    B, U, W, S, Q = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q
+    N0 = pb32.N0
+    pbm = ocd.problem(B, U, W, S, Q, 1, "mmse", "f32", N0)
+    outs = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
+             torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
+
+    def best_plan(prob, ins, o, cands):
+        best = None
+        for c in cands:
+            pl = ocd.Plan(c[0], c[1], c[2], 0)
+            try:
+                f = (lambda: ocd.ocd_detect_mmse(prob, ins["H"], ins["y"], o[0], o[1], pl))
+                f()
+            except ocd.OCDError:
+                continue
+            t = kernel_durations(torch, [f], rounds=3)
+            if best is None or t < best[0]:
+                best = (t, pl)
+        return best[1]
+
+    cands = [(16, 14, 0), (16, 28, 0), (16, 14, 1), (32, 14, 0), (8, 14, 0), (8, 28, 0),
+             (16, 7, 0), (32, 7, 0), (16, 16, 0)]
+    plan = best_plan(pbm, slots[0], outs[0], cands)
+    fns = [(lambda i=i: ocd.ocd_detect_mmse(pbm, slots[i]["H"], slots[i]["y"], outs[i][0],
+                                            outs[i][1], plan)) for i in range(len(slots))]
+    tk = kernel_durations(torch, fns)
+    t, _ = time_graph(torch, GraphedSteps(torch, fns), args.steps, args.warmup)
+    errs = sum(int(((outs[i][1] > 0).to(torch.uint8) != slots[i]["bits"]).sum().item())
+               for i in range(len(slots)))
+    flops, nbytes = algorithmic_mmse(B, U, S, Q)
+    res = {
+        "gbps": W * S * U * Q / t / 1e9, "ms_per_step": t * 1e3, "avg_kernel_us": tk * 1e6,
+        "speedup_vs_ocd_k3": t_ocd / t, "bit_errors_mmse": errs, "bit_errors_ocd_k3": errs_ocd,
+        "bits": nbits, "tflops": flops * W * S / t / 1e12,
+        "hbm_frac": nbytes * W * S / t / 1e9 / HBM_PEAK_GBPS, "plan": plan.as_dict(),
+        "kernel": "ocd::k_mmse<%d, %d, false>" % (plan.lanes_per_vector,
+                                                  max(2, 1 << math.ceil(math.log2(
+                                                      max(2, math.ceil(B / plan.lanes_per_vector)))))),
+    }
+    del outs
+    # S = 1: every vector has its own H
+    W1 = W * S
+    pb1 = ocd.problem(B, U, W1, 1, Q, 1, "mmse", "f32", N0)
+    ins = [synth.make_workload_device(B, U, W1, 1, Q, 20.0, seed=2000 + i, device=dev)
+           for i in range(4)]
+    o1 = [(torch.empty(W1, 1, U, dtype=torch.complex64, device=dev),
+           torch.empty(W1, 1, U, Q, dtype=torch.float32, device=dev)) for _ in ins]
+    plan1 = best_plan(pb1, ins[0], o1[0], [(16, 16, 0), (16, 8, 0), (16, 4, 0), (32, 8, 0),
+                                           (32, 4, 0), (8, 32, 0), (8, 16, 0)])
+    fns = [(lambda i=i: ocd.ocd_detect_mmse(pb1, ins[i]["H"], ins[i]["y"], o1[i][0], o1[i][1],
+                                            plan1)) for i in range(len(ins))]
+    t1, _ = time_graph(torch, GraphedSteps(torch, fns), max(200, args.steps // 4), 20)
+    flops1, bytes1 = algorithmic_mmse(B, U, 1, Q)
+    res["s1"] = {"gbps": W1 * U * Q / t1 / 1e9, "ms_per_step": t1 * 1e3,
+                 "tflops": flops1 * W1 / t1 / 1e12,
+                 "hbm_frac": bytes1 * W1 / t1 / 1e9 / HBM_PEAK_GBPS, "plan": plan1.as_dict()}
+    return res
+
+
 def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     forms = {}
     B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
@@ -463,6 +539,9 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
         "hbm_frac": bytes16 * W * S / t16 / 1e9 / HBM_PEAK_GBPS,
     }
     del s16, o16
+
+    # ---- explicit MMSE (Sections II-B, II-E): the detector OCD approximates
+    forms["exact_mmse"] = mmse_form(torch, ocd, synth, dev, args, slots, pb32, t32, e32, nb)
 
     # ---- S = 1: one channel matrix per vector (HBM-bound shape)
     log("form: S=1 variant")

@@ -214,6 +214,33 @@ ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const *H, const 
                            float *const *z, float *const *llr, int n_jobs,
                            void *workspace, size_t workspace_bytes, int flags, hipStream_t stream);
 
+/* Explicit MMSE soft-output detection, the baseline that OCD approximates without
+ * forming the Gram matrix (Section II-B: regularised Gram matrix and its inverse;
+ * Section II-E: exact channel gain and post-equalisation SINR).  Per subcarrier w,
+ * with lambda = N0/Es:
+ *   G = H_w^H H_w,  A = G + lambda I,  A^-1 (in place, by Gauss-Jordan elimination:
+ *   A is Hermitian positive definite, so no pivoting is needed);
+ *   mu_u = [A^-1 G]_uu = 1 - lambda [A^-1]_uu,  rho_u = mu_u / (1 - mu_u);
+ * and per vector (w, s):
+ *   z = A^-1 (H_w^H y),  L_{u,b} = rho_u (min over O_b^0 |x - a|^2 - min over O_b^1 |x - a|^2)
+ *   at x = z_u / (mu_u sqrt(Es)) against the unit-energy constellation (the same
+ *   sign, labels and layouts as ocd_detect).  A user with an all-zero column gets
+ *   z_u = 0 and LLRs 0.
+ *   pb          mode must be OCD_MMSE (else OCD_EUNSUPPORTED); K is not used;
+ *               B <= 512; FP32 or FP16 storage of H and y as for ocd_detect
+ *   H, y        device [W][U][B], [W][S][B] complex, as for ocd_detect
+ *   z, llr      device outputs [W][S][U] complex FP32 and [W][S][U][Q] FP32, each
+ *               may be NULL (not written), not both
+ *   plan        lanes_per_vector (8, 16 or 32) and vectors_per_block
+ *               (1..512/lanes_per_vector); xcd_remap honoured; channel_in_registers
+ *               must be 0.  NULL: a heuristic choice (whole subcarriers per
+ *               workgroup where they fit).  OCD_EUNSUPPORTED if the plan's LDS
+ *               (H_w of every touched subcarrier plus two U x U work matrices per
+ *               subcarrier) exceeds the device's per-workgroup limit.
+ * Asynchronous on `stream`; no allocation. */
+ocd_status ocd_detect_mmse(const ocd_problem *pb, const void *H, const void *y, float *z,
+                           float *llr, const ocd_plan *plan, hipStream_t stream);
+
 /* Drops every cached hipGraph and pinned staging buffer (e.g. before freeing a
  * workspace that ocd_detect_jobs captured). */
 void ocd_release_graphs(void);

@@ -31,8 +31,10 @@ __all__ = [
     "Problem", "Plan", "OCDError", "MODES", "STORAGES", "LIB_PATH",
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_get_plan", "ocd_set_plan",
-    "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs", "ocd_release_graphs",
-    "problem", "detect", "preprocess", "backward", "detect_jobs", "OCD_JOBS_GRAPH", "OCD_JOBS_TUNE",
+    "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
+    "ocd_release_graphs", "ocd_detect_mmse",
+    "problem", "detect", "preprocess", "backward", "detect_jobs", "detect_mmse", "OCD_JOBS_GRAPH",
+    "OCD_JOBS_TUNE",
     "OCD_JOBS_PERSISTENT", "JobsCall",
 ]
 
@@ -105,6 +107,7 @@ def _load():
         "ocd_detect_jobs": ([P, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(vp), ctypes.c_int, vp, sz, ctypes.c_int, vp], ctypes.c_int),
         "ocd_release_graphs": ([], None),
+        "ocd_detect_mmse": ([P, vp, vp, fp, fp, ctypes.POINTER(Plan), vp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -274,6 +277,17 @@ def ocd_autotune_backward(pb: Problem, H, y, lam, z_hist, dllr, dlam, dbeta, dy,
     return pl
 
 
+def ocd_detect_mmse(pb: Problem, H, y, z=None, llr=None, plan=None, stream=None) -> None:
+    dev = H.device
+    st = _lib.ocd_detect_mmse(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(z, "z", (torch.complex64, torch.float32), pb.W * pb.S * pb.U * 8, dev),
+        _dev_ptr(llr, "llr", (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev),
+        ctypes.byref(plan) if plan is not None else None, _stream(stream))
+    _check("ocd_detect_mmse", st)
+
+
 def _problem_array(jobs):
     arr = (Problem * len(jobs))()
     for i, pb in enumerate(jobs):
@@ -384,6 +398,21 @@ def backward(H, y, z_hist, dllr, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, la
     ws = torch.empty(ocd_backward_workspace_bytes(pb), device=dev, dtype=torch.uint8)
     ocd_detect_backward(pb, H, y, lam, z_hist, dllr, dlam, dbeta, dy, ws, stream)
     return dlam, dbeta, dy
+
+
+def detect_mmse(H, y, Q, N0=1.0, Es=1.0, storage="f32", want_z=True, want_llr=True, plan=None,
+                stream=None):
+    """Runs ocd_detect_mmse (explicit MMSE, exact soft output); returns (z, llr) with None
+    for outputs not asked for.  plan: a Plan, an (L, vectors_per_block[, xcd]) tuple or None."""
+    W, U, B, S = _shape_of(H, y, storage)
+    pb = problem(B, U, W, S, Q, 1, "mmse", storage, N0, Es)
+    dev = H.device
+    z = torch.empty(W, S, U, device=dev, dtype=torch.complex64) if want_z else None
+    llr = torch.empty(W, S, U, Q, device=dev, dtype=torch.float32) if want_llr else None
+    if plan is not None and not isinstance(plan, Plan):
+        plan = Plan(int(plan[0]), int(plan[1]), int(plan[2]) if len(plan) > 2 else 0, 0)
+    ocd_detect_mmse(pb, H, y, z, llr, plan, stream)
+    return z, llr
 
 
 def detect_jobs(jobs, H, y, flags=0, workspace=None, stream=None):

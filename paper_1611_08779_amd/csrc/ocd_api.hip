@@ -376,6 +376,66 @@ extern "C" ocd_status ocd_detect(const ocd_problem *pb, const void *H, const voi
     return run_forward(pb, pl, H, y, lambda, g, dinv, p, z, llr, z_hist, stream);
 }
 
+// ------------------------------------------------------------------ explicit MMSE
+
+namespace ocd {
+
+// Launch parameters of an explicit-MMSE plan; false if the plan does not fit.
+static bool make_mmse_params(const ocd_problem *pb, const ocd_plan &pl, Params &P, int &npl,
+                             int &threads, size_t &lds)
+{
+    const int L = pl.lanes_per_vector;
+    if ((L != 8 && L != 16 && L != 32) || pl.channel_in_registers != 0) return false;
+    if (!make_params(pb, pl, nullptr, false, P, npl, threads, lds) || npl > 16) return false;
+    lds = mmse_lds_bytes(P);
+    return lds <= (size_t)lds_limit_bytes();
+}
+
+// Whole subcarriers per workgroup where they fit in 256 threads, with at most 8
+// entries of a column per lane; fewer vectors while the LDS does not fit.
+static ocd_plan mmse_heuristic_plan(const ocd_problem *pb)
+{
+    int L = 8;
+    while (L < 32 && !(npl_for(pb->B, L) > 0 && npl_for(pb->B, L) <= 8)) L *= 2;
+    const int cap = 256 / L;
+    int v = pb->S <= cap ? (cap / pb->S) * pb->S : cap;
+    ocd_plan pl = {L, v, 0, 0};
+    Params P;
+    int npl, threads;
+    size_t lds;
+    while (pl.vectors_per_block > 1 && !make_mmse_params(pb, pl, P, npl, threads, lds))
+        pl.vectors_per_block = pl.vectors_per_block > pb->S && pl.vectors_per_block % pb->S == 0
+                                   ? pl.vectors_per_block - pb->S
+                                   : pl.vectors_per_block / 2;
+    return pl;
+}
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_detect_mmse(const ocd_problem *pb, const void *H, const void *y,
+                                      float *z, float *llr, const ocd_plan *plan,
+                                      hipStream_t stream)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!H || !y || (!z && !llr)) return OCD_EINVAL;
+    if (pb->mode != OCD_MMSE || pb->B > 512) return OCD_EUNSUPPORTED;
+    const ocd_plan pl = plan ? *plan : mmse_heuristic_plan(pb);
+    Params P;
+    int npl, threads;
+    size_t lds;
+    if (!make_mmse_params(pb, pl, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
+    if (pb->W == 0) return OCD_OK;
+    P.H = H;
+    P.y = y;
+    P.z = reinterpret_cast<float2 *>(z);
+    P.llr = llr;
+    set_vec_ok(P, pb, H, y);
+    const hipError_t e = launch_mmse(pl.lanes_per_vector, npl, pb->storage == OCD_STORE_F16, P,
+                                     threads, lds, stream);
+    return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}
+
 extern "C" ocd_status ocd_get_plan(const ocd_problem *pb, ocd_plan *plan)
 {
     ocd_status st = validate(pb);

@@ -60,6 +60,19 @@ inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward, int nwaves 
     return b;
 }
 
+// Bytes of dynamic LDS of an explicit-MMSE launch: staged H_w, two U x U work
+// matrices and the soft-output coefficients per slot, a matched-filter row per
+// vector and the Gram diagonal per slot.
+inline size_t mmse_lds_bytes(const Params &p)
+{
+    size_t b = (size_t)p.maxslots * p.slot_stride * 8;
+    b += (size_t)p.maxslots * 2 * p.U * p.U * 8;
+    b += (size_t)p.maxslots * p.U * 8;
+    b += (size_t)p.vpb * p.U * 8;
+    b += (size_t)p.maxslots * p.U * 4;
+    return b;
+}
+
 // Launchers (one per template instantiation, selected at run time).
 hipError_t launch_forward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
                           hipStream_t s);
@@ -67,6 +80,8 @@ hipError_t launch_backward(int L, int NPL, bool f16, const Params &p, int thread
                            hipStream_t s);
 hipError_t launch_forward_reg(int L, int NPL, int UC, bool f16, const Params &p,
                               int threads, hipStream_t s);
+hipError_t launch_mmse(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
+                       hipStream_t s);
 hipError_t launch_preprocess(bool f16, const Params &p, float *g, float *dinv, float *pp,
                              hipStream_t s);
 hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s);

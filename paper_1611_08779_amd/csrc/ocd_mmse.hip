@@ -1,0 +1,230 @@
+// ocd_mmse.hip -- explicit MMSE soft-output detection (Section II-B: the
+// regularised Gram matrix and its inverse; Section II-E: exact channel gain and
+// post-equalisation SINR).  This is the detector OCD approximates without forming
+// the Gram matrix; it gives the reference error rate and throughput.
+//
+// One workgroup per tile of vectors, as in the OCD forward kernel: the H_w of the
+// subcarriers a tile touches are staged once into LDS and shared by its vectors.
+//   1. Lane groups form the upper triangle of A = H_w^H H_w + lambda I, one entry
+//      per group at a time (a DPP sum over the group), and mirror it.
+//   2. One wave per subcarrier inverts A in place by Gauss-Jordan elimination.  A
+//      is Hermitian positive definite, so every pivot is a positive Schur
+//      complement and no pivoting is needed.  Each step reads one LDS copy of the
+//      work matrix and writes the other, so no step overwrites what it still reads.
+//   3. A^-1 G = I - lambda A^-1 gives the gain mu_u = 1 - lambda [A^-1]_uu and
+//      1 - mu_u = lambda [A^-1]_uu directly, without cancellation, hence the SINR
+//      rho_u = mu_u / (1 - mu_u) and the soft-output coefficients.
+//   4. Per vector: s = H_w^H y (lane group, DPP sums), then z = A^-1 s with one
+//      (user, axis) pair per lane, and the per-axis max-log LLRs.
+#include "ocd_stage.h"
+
+namespace ocd {
+
+struct MmseSmem {
+    float2 *H;   // [maxslots][slot_stride]: H_w columns, FP32, zero-padded to Bpad
+    float2 *A;   // [maxslots][2][U][U]: the two copies of the elimination's work matrix
+    float *gd;   // [maxslots][U]: diagonal of G (zero for an all-zero column)
+    float2 *lc;  // [maxslots][U]: soft-output coefficients (see llr_coef)
+    float2 *s;   // [vpb][U]: matched-filter output of each vector
+};
+
+__device__ __forceinline__ MmseSmem mmse_carve(unsigned char *smem, const Params &P)
+{
+    MmseSmem s;
+    size_t off = 0;
+    s.H = reinterpret_cast<float2 *>(smem);
+    off += (size_t)P.maxslots * P.slot_stride * 8;
+    s.A = reinterpret_cast<float2 *>(smem + off);
+    off += (size_t)P.maxslots * 2 * P.U * P.U * 8;
+    s.lc = reinterpret_cast<float2 *>(smem + off);
+    off += (size_t)P.maxslots * P.U * 8;
+    s.s = reinterpret_cast<float2 *>(smem + off);
+    off += (size_t)P.vpb * P.U * 8;
+    s.gd = reinterpret_cast<float *>(smem + off);
+    return s;
+}
+
+template <int L, int NPL, bool F16>
+__global__ __launch_bounds__(512) void k_mmse(Params P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const MmseSmem sm = mmse_carve(smem, P);
+    const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const Tile tile = tile_of(P, bid);
+    const int U = P.U, Bpad = P.Bpad, E = U * U;
+    const int grp = threadIdx.x / L, j = threadIdx.x % L, ngrp = blockDim.x / L;
+    const bool active = grp < tile.nvb;
+    const float lam = P.lam_default;
+
+    // H_w chunk loads, then the receive vector: both round trips in flight together
+    Smem hs = {};
+    hs.H = sm.H;
+    const int chunks = tile.nslots * U * (Bpad >> 1);
+    float4 hbuf[STAGE_CHUNKS];
+    stage_h_load<F16>(P, tile.w_first, tile.nslots, chunks, 0, hbuf);
+    float2 r[NPL];
+    load_vector<L, NPL, F16>(P, P.y, tile, grp, j, active, r);
+    stage_h_store(P, hs, tile.nslots, chunks, 0, hbuf);
+    stage_h_copy<F16>(P, hs, tile.w_first, tile.nslots, chunks, STAGE_CHUNKS * (int)blockDim.x);
+    __syncthreads();
+    clear_padding<L, NPL>(P, j, active, r);
+
+    // 1. upper triangle of A = G + lambda I (entry (i, c), c >= i), mirrored below
+    const int T = U * (U + 1) / 2;
+    for (int t = grp; t < tile.nslots * T; t += ngrp) {
+        const int sl = t / T;
+        int q = t - sl * T, i = 0;
+        while (q >= U - i) {   // row i of the triangle holds U - i entries
+            q -= U - i;
+            ++i;
+        }
+        const int c = i + q;
+        const float2 *Hs = sm.H + (size_t)sl * P.slot_stride;
+        float2 hi[NPL], hc[NPL];
+        load_column<L, NPL>(Hs + (size_t)i * Bpad, j, hi);
+        load_column<L, NPL>(Hs + (size_t)c * Bpad, j, hc);
+        float re = 0.f, im = 0.f;   // conj(h_i)^T h_c over this lane's entries
+#pragma unroll
+        for (int e = 0; e < NPL; ++e) {
+            re = fmaf(hi[e].x, hc[e].x, fmaf(hi[e].y, hc[e].y, re));
+            im = fmaf(hi[e].x, hc[e].y, fmaf(-hi[e].y, hc[e].x, im));
+        }
+        re = group_sum<L>(re);
+        im = group_sum<L>(im);
+        if (j == 0) {
+            float2 *A = sm.A + (size_t)sl * 2 * E;
+            if (i == c) {
+                A[i * U + i] = make_float2(re + lam, 0.f);
+                sm.gd[sl * U + i] = re;
+            } else {
+                A[i * U + c] = make_float2(re, im);
+                A[c * U + i] = make_float2(re, -im);
+            }
+        }
+    }
+    __syncthreads();
+
+    // 2. Gauss-Jordan inversion in place, one wave per staged subcarrier.  Step k
+    // maps the work matrix M to M' with
+    //   M'_kk = 1/M_kk,  M'_kc = M_kc / M_kk,  M'_ik = -M_ik / M_kk,
+    //   M'_ic = M_ic - M_ik M_kc / M_kk  (i, c != k);
+    // after U steps M' = A^-1.  The lanes of a wave issue their LDS operations in
+    // program order, so step k + 1 sees every write of step k.
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    for (int sl = wave; sl < tile.nslots; sl += nwaves) {
+        float2 *A0 = sm.A + (size_t)sl * 2 * E;
+        for (int k = 0; k < U; ++k) {
+            const float2 *src = A0 + (k & 1) * E;
+            float2 *dst = A0 + ((k + 1) & 1) * E;
+            const float piv = 1.0f / src[k * U + k].x;   // Hermitian: a real pivot
+            const float2 *rowk = src + k * U;
+            for (int e = lane; e < E; e += 64) {
+                const int i = e / U, c = e - i * U;
+                const float2 aik = src[i * U + k], akc = rowk[c], aic = src[e];
+                float2 out;
+                if (i == k) {
+                    out = c == k ? make_float2(piv, 0.f) : make_float2(akc.x * piv, akc.y * piv);
+                } else if (c == k) {
+                    out = make_float2(-aik.x * piv, -aik.y * piv);
+                } else {
+                    const float mx = aik.x * akc.x - aik.y * akc.y;
+                    const float my = aik.x * akc.y + aik.y * akc.x;
+                    out = make_float2(fmaf(-mx, piv, aic.x), fmaf(-my, piv, aic.y));
+                }
+                dst[e] = out;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // 3. gain, SINR and the soft-output coefficients of each user
+        const float2 *Ai = A0 + (U & 1) * E;
+        for (int u = lane; u < U; u += 64) {
+            const float one_minus_mu = lam * Ai[u * U + u].x;
+            const float mu = 1.0f - one_minus_mu, rho = mu / one_minus_mu;
+            float2 co = make_float2(0.f, 0.f);
+            if (sm.gd[sl * U + u] > 0.f && mu > 0.f && rho > 0.f)
+                co = make_float2(1.0f / (mu * P.sqEs * P.qscale), rho * P.qscale * P.qscale);
+            sm.lc[sl * U + u] = co;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    // 4. matched filter s = H_w^H y; lane u mod L keeps s_u in the vector's LDS row
+    const int slot = slot_of_group(P, tile, grp);
+    const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
+    float2 *sv = sm.s + (size_t)grp * U;
+    for (int u = 0; u < U; ++u) {
+        float2 h[NPL];
+        load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int e = 0; e < NPL; ++e) {
+            re = fmaf(h[e].x, r[e].x, fmaf(h[e].y, r[e].y, re));
+            im = fmaf(h[e].x, r[e].y, fmaf(-h[e].y, r[e].x, im));
+        }
+        re = group_sum<L>(re);
+        im = group_sum<L>(im);
+        if (j == (u & (L - 1))) sv[u] = make_float2(re, im);
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // z = A^-1 s: lane pair index idx = 2u + axis computes one real component
+    const float2 *Ai = sm.A + (size_t)slot * 2 * E + (U & 1) * E;
+    const long v = (long)tile.vbase + grp;
+    const int Q = P.Q, half = Q >> 1;
+    for (int idx = j; idx < 2 * U; idx += L) {
+        const int u = idx >> 1, ax = idx & 1;
+        const float2 *row = Ai + (size_t)u * U;
+        float acc = 0.f;
+        for (int c = 0; c < U; ++c) {
+            const float2 a = row[c], s = sv[c];
+            // Re: a.x s.x - a.y s.y;  Im: a.x s.y + a.y s.x
+            const float s1 = ax ? s.y : s.x, s2 = ax ? s.x : -s.y;
+            acc = fmaf(a.x, s1, fmaf(a.y, s2, acc));
+        }
+        if (P.z) reinterpret_cast<float *>(P.z)[v * 2 * U + idx] = acc;
+        if (P.llr) {
+            const float2 co = sm.lc[slot * U + u];
+            float *dst = P.llr + (v * U + u) * Q + ax * half;
+            const float t = acc * co.x;
+            if (half == 3) axis_llrs<3>(t, co.y, dst);
+            else if (half == 2) axis_llrs<2>(t, co.y, dst);
+            else axis_llrs<1>(t, co.y, dst);
+        }
+    }
+}
+
+template <int L, int NPL>
+static hipError_t launch_mmse_t(bool f16, const Params &p, int threads, size_t lds, hipStream_t s)
+{
+    const dim3 grid(p.nblocks), block(threads);
+    if (f16) hipLaunchKernelGGL((k_mmse<L, NPL, true>), grid, block, lds, s, p);
+    else hipLaunchKernelGGL((k_mmse<L, NPL, false>), grid, block, lds, s, p);
+    return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_mmse_l(int NPL, bool f16, const Params &p, int threads, size_t lds,
+                                hipStream_t s)
+{
+    switch (NPL) {
+    case 2: return launch_mmse_t<L, 2>(f16, p, threads, lds, s);
+    case 4: return launch_mmse_t<L, 4>(f16, p, threads, lds, s);
+    case 8: return launch_mmse_t<L, 8>(f16, p, threads, lds, s);
+    case 16: return launch_mmse_t<L, 16>(f16, p, threads, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_mmse(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
+                       hipStream_t s)
+{
+    switch (L) {
+    case 8: return launch_mmse_l<8>(NPL, f16, p, threads, lds, s);
+    case 16: return launch_mmse_l<16>(NPL, f16, p, threads, lds, s);
+    case 32: return launch_mmse_l<32>(NPL, f16, p, threads, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ocd

@@ -173,3 +173,42 @@ def test_register_plans_are_checked_on_the_host(lib, over, plan, status):
     lib.ocd_set_plan.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Plan)]
     pb = Problem(**{**_good(), **over})
     assert lib.ocd_set_plan(ctypes.byref(pb), ctypes.byref(Plan(*plan))) == status
+
+
+def test_mmse_detector_checks_its_arguments_on_the_host(lib):
+    lib.ocd_detect_mmse.restype = ctypes.c_int
+    lib.ocd_detect_mmse.argtypes = [ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Plan),
+                                    ctypes.c_void_p]
+    d = ctypes.c_void_p(0x1000)
+
+    def call(over=None, H=d, y=d, z=d, llr=d, plan=None):
+        pb = Problem(**{**_good(), **(over or {})})
+        return lib.ocd_detect_mmse(ctypes.byref(pb), H, y, z, llr,
+                                   ctypes.byref(Plan(*plan)) if plan else None, None)
+
+    assert call(H=None) == -1
+    assert call(y=None) == -1
+    assert call(z=None, llr=None) == -1
+    assert call(dict(B=0)) == -1
+    assert call(dict(mode=1)) == -2                     # no closed form for the box problem
+    assert call(dict(mode=2)) == -2
+    assert call(dict(B=600)) == -2                      # above the kernel's antenna bound
+    assert call(plan=(4, 16, 0, 0)) == -2               # lane groups of 8, 16 or 32
+    assert call(plan=(16, 14, 0, 1)) == -2              # channel in registers: OCD only
+    assert call(plan=(16, 33, 0, 0)) == -2              # more than 512 lanes per workgroup
+    assert call(dict(W=0), plan=(16, 14, 0, 0)) == 0    # nothing to do
+
+
+@pytest.mark.parametrize("B,U,S", [(512, 8, 2), (256, 16, 3), (128, 8, 14), (64, 32, 2), (33, 4, 2),
+                                   (100, 8, 3), (16, 1, 5)])
+def test_mmse_heuristic_plan_fits(lib, B, U, S):
+    """The default plan of ocd_detect_mmse is valid for every shape whose single
+    subcarrier fits the 64 KiB of LDS assumed without a device (W = 0: nothing runs)."""
+    lib.ocd_detect_mmse.restype = ctypes.c_int
+    lib.ocd_detect_mmse.argtypes = [ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Plan),
+                                    ctypes.c_void_p]
+    d = ctypes.c_void_p(0x1000)
+    pb = Problem(**{**_good(), "B": B, "U": U, "S": S, "W": 0})
+    assert lib.ocd_detect_mmse(ctypes.byref(pb), d, d, d, d, None, None) == 0
