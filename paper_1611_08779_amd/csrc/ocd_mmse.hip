@@ -14,8 +14,9 @@
 //   3. A^-1 G = I - lambda A^-1 gives the gain mu_u = 1 - lambda [A^-1]_uu and
 //      1 - mu_u = lambda [A^-1]_uu directly, without cancellation, hence the SINR
 //      rho_u = mu_u / (1 - mu_u) and the soft-output coefficients.
-//   4. Per vector: s = H_w^H y (lane group, DPP sums), then z = A^-1 s with one
-//      (user, axis) pair per lane, and the per-axis max-log LLRs.
+//   4. Per vector: s = H_w^H y (lane group, DPP sums; it overlaps step 2 on the
+//      waves that do not invert), then z = A^-1 s with one (user, axis) pair per
+//      lane, and the per-axis max-log LLRs.
 #include "ocd_stage.h"
 
 namespace ocd {
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(512) void k_mmse(Params P)
             const float piv = 1.0f / src[k * U + k].x;   // Hermitian: a real pivot
             const float2 *rowk = src + k * U;
             for (int e = lane; e < E; e += 64) {
-                const int i = e / U, c = e - i * U;
+                const int i = slot_of_row(P, e), c = e - i * U;   // e / U (e < 2^10)
                 const float2 aik = src[i * U + k], akc = rowk[c], aic = src[e];
                 float2 out;
                 if (i == k) {
@@ -146,27 +147,29 @@ __global__ __launch_bounds__(512) void k_mmse(Params P)
             sm.lc[sl * U + u] = co;
         }
     }
+
+    // 4. matched filter s = H_w^H y (needs only the staged H_w, so the other waves
+    // run it while a wave inverts); lane u mod L keeps s_u in the vector's LDS row
+    const int slot = slot_of_group(P, tile, active ? grp : 0);
+    float2 *sv = sm.s + (size_t)(active ? grp : 0) * U;
+    if (active) {
+        const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
+        for (int u = 0; u < U; ++u) {
+            float2 h[NPL];
+            load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
+            float re = 0.f, im = 0.f;
+#pragma unroll
+            for (int e = 0; e < NPL; ++e) {
+                re = fmaf(h[e].x, r[e].x, fmaf(h[e].y, r[e].y, re));
+                im = fmaf(h[e].x, r[e].y, fmaf(-h[e].y, r[e].x, im));
+            }
+            re = group_sum<L>(re);
+            im = group_sum<L>(im);
+            if (j == (u & (L - 1))) sv[u] = make_float2(re, im);
+        }
+    }
     __syncthreads();
     if (!active) return;
-
-    // 4. matched filter s = H_w^H y; lane u mod L keeps s_u in the vector's LDS row
-    const int slot = slot_of_group(P, tile, grp);
-    const float2 *Hs = sm.H + (size_t)slot * P.slot_stride;
-    float2 *sv = sm.s + (size_t)grp * U;
-    for (int u = 0; u < U; ++u) {
-        float2 h[NPL];
-        load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
-        float re = 0.f, im = 0.f;
-#pragma unroll
-        for (int e = 0; e < NPL; ++e) {
-            re = fmaf(h[e].x, r[e].x, fmaf(h[e].y, r[e].y, re));
-            im = fmaf(h[e].x, r[e].y, fmaf(-h[e].y, r[e].x, im));
-        }
-        re = group_sum<L>(re);
-        im = group_sum<L>(im);
-        if (j == (u & (L - 1))) sv[u] = make_float2(re, im);
-    }
-    __builtin_amdgcn_wave_barrier();
 
     // z = A^-1 s: lane pair index idx = 2u + axis computes one real component
     const float2 *Ai = sm.A + (size_t)slot * 2 * E + (U & 1) * E;
