@@ -51,8 +51,13 @@ def _open(path):
     lib.oracle_ocd_trace.argtypes = [i, i, i, i, i, d, d, dp, d, dp, dp, dp]
     lib.oracle_constellation.argtypes = [i, dp, ctypes.POINTER(ctypes.c_uint)]
     lib.oracle_mmse.argtypes = [i, i, i, i, i, d, d, dp, dp, dp, dp, dp, i]
+    sp = ctypes.POINTER(ctypes.c_int16)
+    lib.oracle_ocd_fixed.argtypes = [i, i, i, i, i, i, i, d, d, d, sp, sp, sp, dp, i]
+    lib.oracle_fx_recip.argtypes = [ctypes.c_int64]
+    lib.oracle_fx_recip.restype = ctypes.c_int64
     for f in ("oracle_ocd", "oracle_cd", "oracle_llr", "oracle_detect", "oracle_hard",
-              "oracle_grad", "oracle_ocd_trace", "oracle_constellation", "oracle_mmse"):
+              "oracle_grad", "oracle_ocd_trace", "oracle_constellation", "oracle_mmse",
+              "oracle_ocd_fixed"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -235,3 +240,31 @@ def mmse(H, y, Q, N0=1.0, Es=1.0, threads=1):
     if rc:
         raise ValueError("oracle_mmse rejected its arguments")
     return z, out, mu
+
+
+def _i16(a):
+    return np.ascontiguousarray(np.asarray(a), dtype=np.int16)
+
+
+def ocd_fixed(Hq, yq, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, threads=1):
+    """Algorithm 1 in the fixed-point datapath of Section IV-C (readings F1-F8 in
+    ocd_oracle.c).  Hq [W,U,B,2], yq [W,S,B,2] int16 Q5.11 -> z [W,S,U,2] int16 and
+    LLRs [W,S,U,Q] (floating point from the fixed-point z and p)."""
+    lib = _load()
+    Hq, yq = _i16(Hq), _i16(yq)
+    W, U, B, _ = Hq.shape
+    S = yq.shape[1]
+    z = np.zeros((W, S, U, 2), np.int16)
+    out = np.zeros((W, S, U, Q), np.float64)
+    sp = ctypes.POINTER(ctypes.c_int16)
+    rc = lib.oracle_ocd_fixed(B, U, W, S, K, Q, MODES[mode], float(N0), float(Es), float(beta),
+                              Hq.ctypes.data_as(sp), yq.ctypes.data_as(sp), z.ctypes.data_as(sp),
+                              _ptr(out), _threads(threads))
+    if rc:
+        raise ValueError("oracle_ocd_fixed rejected its arguments or a sum left 36 bits")
+    return z, out
+
+
+def fx_recip(x):
+    """The fixed-point reciprocal unit (reading F5): Q.22 integer x -> Q.11 integer."""
+    return int(_load().oracle_fx_recip(int(x)))

@@ -68,10 +68,17 @@
  *                U = 1 and orthogonal-column closed forms (where the LLRs equal
  *                oracle_ocd's at K = 1); mu_i^2 Es / E|z_i - mu_i s_i|^2 =
  *                rho_i from the explicit error covariance; 0 < mu_i < 1.
+ *   oracle_ocd_fixed  the reciprocal unit against the true reciprocal; exact
+ *                recovery on exactly representable orthogonal channels; within
+ *                4 LSB of oracle_ocd on the dequantised inputs; zero-mean
+ *                rounding error; saturation and clipping in closed form; the
+ *                36-bit range check.  The value of b (F3) only moves rounding by
+ *                LSBs (its two shifts cancel): parity unpinned beyond the reading.
  */
 #include <complex.h>
 #include <math.h>
 #include <stdlib.h>
+#include <stdint.h>
 #include <string.h>
 
 #ifdef _OPENMP
@@ -726,5 +733,194 @@ int oracle_mmse(int B, int U, int W, int S, int Q, double N0, double Es, const d
         }
         free(G); free(A); free(Lf); free(Ainv); free(mf); free(mu); free(rho);
     }
+    return failed ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The fixed-point datapath of Section IV-C (readings F1-F8)               */
+/* ---------------------------------------------------------------------- */
+/*
+ * F1  Words.  H, y, the residual r, z, beta, d^-1 and p are 16-bit two's
+ *     complement with 11 fractional bits (Q5.11: value = integer / 2^11).
+ *     Products of two such words are exact (Q.22); the inner products are
+ *     exact sums of them (the paper's 36-bit adder tree; the oracle fails if a
+ *     sum leaves the 36-bit range, so "exact" and "36-bit" agree).
+ * F2  Scale.  The shifts below assume channel entries of unit average power
+ *     (||h_u||^2 close to B); a caller with another channel scale multiplies H
+ *     and y by one factor c and N0 by c^2, which leaves OCD's estimate unchanged.
+ * F3  b = ceil(log2 B).  ||h_u||^2 + alpha and h_u^H r are shifted right by b
+ *     (arithmetic shift: floor); the two shifts cancel in d^-1 h^H r.
+ * F4  alpha = lambda (N0/Es in MMSE mode, 0 in BOX mode) enters as the Q.22
+ *     integer round(lambda 2^22).
+ * F5  Reciprocal of an integer x > 0 of bit length n (x / 2^n in [1/2, 1)):
+ *     the index is the 11 bits after the leading one; the table holds the 18-bit
+ *     normalised reciprocal round(2^18 / (1 + (i + 1/2) / 2048)) (1/x in Q1.17
+ *     at the middle of the index's interval); denormalising to Q.11 multiplies by
+ *     2^(16 - n) (x is in Q.22 units).  x = 0 gives 0.
+ * F6  Every narrowing to 16 bits rounds half up (add half an LSB, shift) and
+ *     saturates to [-2^15, 2^15 - 1].
+ * F7  p_u = d_u^-1 (||h_u||^2 >> b), narrowed to Q.11 (F6).
+ * F8  The FPGA design has no soft-output unit: LLRs are formed in floating
+ *     point from the fixed-point z (mu = p / 2^11 in MMSE mode, 1 in BOX mode;
+ *     rho = g / lambda, g = ||h_u||^2 / 2^22; BOX: g Es / N0), as in R3.
+ */
+
+#define FX_FRAC 11
+#define FX_ACC_BITS 36
+
+static int64_t fx_sat16(int64_t v)
+{
+    return v < -32768 ? -32768 : (v > 32767 ? 32767 : v);
+}
+
+/* v / 2^s rounded half up, s >= 1. */
+static int64_t fx_round_shift(int64_t v, int s) { return (v + ((int64_t)1 << (s - 1))) >> s; }
+
+static int fx_bitlen(uint64_t x)
+{
+    int n = 0;
+    while (x) { ++n; x >>= 1; }
+    return n;
+}
+
+/* F5 */
+static int64_t fx_recip(int64_t x)
+{
+    if (x <= 0) return 0;
+    int n = fx_bitlen((uint64_t)x);
+    int64_t idx = n >= 12 ? (x >> (n - 12)) & 2047 : (x << (12 - n)) & 2047;
+    int64_t lut = (int64_t)floor(262144.0 / (1.0 + ((double)idx + 0.5) / 2048.0) + 0.5);
+    int64_t d = (16 - n >= 0) ? lut << (16 - n) : fx_round_shift(lut, n - 16);
+    return fx_sat16(d);
+}
+
+/* Exported for tests: the reciprocal unit alone. */
+int64_t oracle_fx_recip(int64_t x) { return fx_recip(x); }
+
+static int fx_ceil_log2(int B)
+{
+    int b = 0;
+    while ((1 << b) < B) ++b;
+    return b;
+}
+
+static int fx_acc_ok(int64_t v)
+{
+    const int64_t lim = (int64_t)1 << (FX_ACC_BITS - 1);
+    return v >= -lim && v < lim;
+}
+
+/* Algorithm 1 in the fixed-point datapath, one vector.  h: U columns of B
+ * (re, im) int16 pairs; yv: B pairs; z: U pairs out; p_out: p_u of the sweeps
+ * (F7).  Returns -1 if an inner product leaves the 36-bit range. */
+static int ocd_fixed_one(int B, int U, int K, int box, int64_t lam_q, int64_t beta_fx,
+                         const int16_t *h, const int16_t *yv, int16_t *zout, int64_t *G,
+                         int64_t *dinv, int64_t *p)
+{
+    const int b = fx_ceil_log2(B);
+    int64_t *r = malloc(sizeof(int64_t) * 2 * B), *z = malloc(sizeof(int64_t) * 2 * U);
+    int ok = 1;
+    for (int i = 0; i < 2 * B; ++i) r[i] = yv[i];
+    for (int u = 0; u < 2 * U; ++u) z[u] = 0;
+    /* preprocessing (Alg. 1, initialisation) */
+    for (int u = 0; u < U; ++u) {
+        const int16_t *hu = h + (size_t)2 * u * B;
+        int64_t g = 0;
+        for (int i = 0; i < B; ++i) g += (int64_t)hu[2 * i] * hu[2 * i] + (int64_t)hu[2 * i + 1] * hu[2 * i + 1];
+        ok &= fx_acc_ok(g);
+        G[u] = g;
+        dinv[u] = fx_recip((g + lam_q) >> b);
+        p[u] = fx_sat16(fx_round_shift(dinv[u] * (g >> b), 22));
+    }
+    for (int k = 0; k < K; ++k)
+        for (int u = 0; u < U; ++u) {
+            const int16_t *hu = h + (size_t)2 * u * B;
+            int64_t ire = 0, iim = 0;      /* h_u^H r, Q.22 */
+            for (int i = 0; i < B; ++i) {
+                const int64_t hr = hu[2 * i], hi = hu[2 * i + 1];
+                ire += hr * r[2 * i] + hi * r[2 * i + 1];
+                iim += hr * r[2 * i + 1] - hi * r[2 * i];
+            }
+            ok &= fx_acc_ok(ire) && fx_acc_ok(iim);
+            ire >>= b;
+            iim >>= b;
+            /* c = d^-1 (h^H r) + p z, in Q.33, narrowed to Q.11 */
+            int64_t cre = fx_sat16(fx_round_shift(dinv[u] * ire + (p[u] * z[2 * u] << 11), 22));
+            int64_t cim = fx_sat16(fx_round_shift(dinv[u] * iim + (p[u] * z[2 * u + 1] << 11), 22));
+            if (box) {
+                if (cre > beta_fx) cre = beta_fx;
+                if (cre < -beta_fx) cre = -beta_fx;
+                if (cim > beta_fx) cim = beta_fx;
+                if (cim < -beta_fx) cim = -beta_fx;
+            }
+            const int64_t dre = cre - z[2 * u], dim = cim - z[2 * u + 1];
+            for (int i = 0; i < B; ++i) {
+                const int64_t hr = hu[2 * i], hi = hu[2 * i + 1];
+                r[2 * i] = fx_sat16(r[2 * i] - fx_round_shift(hr * dre - hi * dim, FX_FRAC));
+                r[2 * i + 1] = fx_sat16(r[2 * i + 1] - fx_round_shift(hr * dim + hi * dre, FX_FRAC));
+            }
+            z[2 * u] = cre;
+            z[2 * u + 1] = cim;
+        }
+    for (int u = 0; u < 2 * U; ++u) zout[u] = (int16_t)z[u];
+    free(r); free(z);
+    return ok ? 0 : -1;
+}
+
+/* Every vector through the fixed-point datapath, then the soft output (F8).
+ * H [W][U][B] and y [W][S][B] int16 (re, im) pairs in Q5.11; z [W][S][U] pairs
+ * (may be NULL); llr [W][S][U][Q] (may be NULL).  mode: MMSE or BOX. */
+int oracle_ocd_fixed(int B, int U, int W, int S, int K, int Q, int mode, double N0, double Es,
+                     double beta, const int16_t *H, const int16_t *y, int16_t *z, double *llr,
+                     int threads)
+{
+    problem P;
+    if (mode == MODE_HYBRID) return -1;
+    if (setup(&P, B, U, W, S, K, Q, mode, N0, Es, NULL, beta)) return -1;
+    const double lam = P.lambda[0];
+    const int64_t lam_q = (int64_t)floor(lam * 4194304.0 + 0.5);
+    const int64_t beta_fx = (int64_t)floor(P.beta * 2048.0 + 0.5);
+    cplx pts[64];
+    unsigned labels[64];
+    qam_points(Q, pts, labels);
+    int failed = 0;
+    const long nvec = (long)W * S;
+#pragma omp parallel num_threads(threads > 0 ? threads : 1)
+    {
+        int16_t *zv = malloc(sizeof(int16_t) * 2 * U);
+        int64_t *G = malloc(sizeof(int64_t) * U), *dinv = malloc(sizeof(int64_t) * U);
+        int64_t *p = malloc(sizeof(int64_t) * U);
+#pragma omp for schedule(static)
+        for (long v = 0; v < nvec; ++v) {
+            const int16_t *h = H + (size_t)(v / S) * U * B * 2;
+            if (ocd_fixed_one(B, U, K, P.box, lam_q, beta_fx, h, y + (size_t)v * B * 2, zv, G,
+                              dinv, p)) {
+#pragma omp atomic write
+                failed = 1;
+            }
+            if (z) memcpy(z + (size_t)v * U * 2, zv, sizeof(int16_t) * 2 * U);
+            if (!llr) continue;
+            for (int u = 0; u < U; ++u) {
+                double *Lout = llr + ((size_t)v * U + u) * Q;
+                const double g = (double)G[u] / 4194304.0;
+                double mu, rho;
+                if (lam > 0.0) {
+                    mu = (double)p[u] / 2048.0;
+                    rho = g / lam;
+                } else {
+                    mu = 1.0;
+                    rho = g * Es / N0;
+                }
+                if (!(mu > 0.0) || !(rho > 0.0)) {
+                    for (int bq = 0; bq < Q; ++bq) Lout[bq] = 0.0;
+                    continue;
+                }
+                const cplx zu = ((double)zv[2 * u] + I * (double)zv[2 * u + 1]) / 2048.0;
+                maxlog_one(Q, pts, labels, zu / (mu * sqrt(Es)), rho, Lout, NULL, NULL);
+            }
+        }
+        free(zv); free(G); free(dinv); free(p);
+    }
+    free(P.lambda);
     return failed ? -1 : 0;
 }

@@ -13,6 +13,7 @@ import subprocess
 import pytest
 
 import oracle
+import test_oracle_fixed_pins as fpins
 import test_oracle_mmse_pins as mpins
 import test_oracle_pins as pins
 
@@ -57,6 +58,20 @@ MUTANTS = [
      "s += Ainv[j * U + i] * G[j * U + i];"),
     ("exact SINR taken as mu", "rho[i] = mu[i] / (1.0 - mu[i]);", "rho[i] = mu[i];"),
     ("exact LLR point ignores the gain", "zi / (mu[i] * sqrt(Es))", "zi / sqrt(Es)"),
+    # fixed-point datapath (Section IV-C)
+    ("fixed: p z dropped", "dinv[u] * ire + (p[u] * z[2 * u] << 11)", "dinv[u] * ire"),
+    ("fixed: inner product without the conjugate", "ire += hr * r[2 * i] + hi * r[2 * i + 1];",
+     "ire += hr * r[2 * i] - hi * r[2 * i + 1];"),
+    ("fixed: table at interval starts", "((double)idx + 0.5) / 2048.0", "((double)idx) / 2048.0"),
+    ("fixed: 10-bit table index", "(x >> (n - 12)) & 2047", "(x >> (n - 11)) & 1023"),
+    ("fixed: truncation instead of rounding", "return (v + ((int64_t)1 << (s - 1))) >> s;",
+     "return v >> s;"),
+    ("fixed: no saturation", "return v < -32768 ? -32768 : (v > 32767 ? 32767 : v);", "return v;"),
+    ("fixed: residual update sign", "r[2 * i] = fx_sat16(r[2 * i] - fx_round_shift(",
+     "r[2 * i] = fx_sat16(r[2 * i] + fx_round_shift("),
+    ("fixed: one-sided clip", "if (cre < -beta_fx) cre = -beta_fx;", ""),
+    ("fixed: p without the shift", "fx_round_shift(dinv[u] * (g >> b), 22)",
+     "fx_round_shift(dinv[u] * g, 22)"),
 ]
 
 BATTERY = [
@@ -86,6 +101,13 @@ BATTERY = [
     lambda: mpins.test_single_user_closed_form(4),
     lambda: mpins.test_orthogonal_columns_equal_one_ocd_sweep(6),
     lambda: mpins.test_high_snr_llr_signs_are_the_transmitted_bits(),
+    lambda: fpins.test_reciprocal_unit_error_bound(22),
+    lambda: fpins.test_exact_orthogonal_channels_recover_the_symbols("mmse", 3),
+    lambda: fpins.test_exact_orthogonal_channels_recover_the_symbols("box", 3),
+    lambda: fpins.test_close_to_the_floating_point_oracle(100, 6, "mmse"),
+    lambda: fpins.test_close_to_the_floating_point_oracle(128, 8, "box"),
+    lambda: fpins.test_rounding_is_unbiased(),
+    lambda: fpins.test_saturation_and_box_clip_closed_form(),
 ]
 
 
