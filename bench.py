@@ -288,6 +288,9 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="L,VPB[,XCD]: fix the launch plan instead of autotuning (profiled runs, "
                          "so that every traced launch of the kernel is the timed one)")
+    ap.add_argument("--mmse-only", default=None, metavar="L,VPB",
+                    help="only the explicit-MMSE detector on the headline slots with this plan "
+                         "(profiled runs); prints its own JSON line")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DIR", default=None,
                     help="no GPU work: summarise rocprofv3 CSV output (a --kernel-trace --stats "
                          "directory, or FETCH_SIZE and WRITE_SIZE --pmc directories) and exit")
@@ -333,6 +336,20 @@ def main():
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
     outs = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
              torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
+    if args.mmse_only:
+        f = [int(x) for x in args.mmse_only.split(",")] + [0]
+        mp = ocd.Plan(f[0], f[1], f[2], 0)
+        pbm = ocd.problem(B, U, W, S, Q, 1, "mmse", "f32", N0)
+        fns = [(lambda i=i: ocd.ocd_detect_mmse(pbm, slots[i]["H"], slots[i]["y"], outs[i][0],
+                                                outs[i][1], mp)) for i in range(len(slots))]
+        tk = kernel_durations(torch, fns)
+        t, n = time_graph(torch, GraphedSteps(torch, fns), args.steps, args.warmup)
+        flops, nbytes = algorithmic_mmse(B, U, S, Q)
+        print(json.dumps({"form": "exact_mmse", "plan": mp.as_dict(), "steps": n,
+                          "avg_kernel_us": t * 1e6, "single_eager_launch_us": tk * 1e6,
+                          "gbps": W * S * U * Q / t / 1e9, "tflops": flops * W * S / t / 1e12,
+                          "hbm_frac": nbytes * W * S / t / 1e9 / HBM_PEAK_GBPS}), flush=True)
+        return
     if args.plan:
         f = [int(x) for x in args.plan.split(",")] + [0]
         plan = ocd.Plan(f[0], f[1], f[2], 0)

@@ -50,6 +50,7 @@
 #define OCD_H
 
 #include <stddef.h>
+#include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
 #ifdef __cplusplus
@@ -240,6 +241,33 @@ ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const *H, const 
  * Asynchronous on `stream`; no allocation. */
 ocd_status ocd_detect_mmse(const ocd_problem *pb, const void *H, const void *y, float *z,
                            float *llr, const ocd_plan *plan, hipStream_t stream);
+
+/* Algorithm 1 in the paper's fixed-point datapath (Section IV-C), for comparison
+ * with the floating-point path on the same inputs.  Words are 16-bit with 11
+ * fractional bits (Q5.11: value = integer / 2048).  Per vector:
+ *   preprocessing  g_u = ||h_u||^2 (exact, Q.22), d_u^-1 = R((g_u + alpha) >> b),
+ *                  p_u = d_u^-1 (g_u >> b) narrowed to Q.11, with b = ceil(log2 B) and
+ *                  alpha = round(lambda 2^22) (lambda = N0/Es in MMSE mode, 0 in BOX);
+ *   each update    c = d_u^-1 ((h_u^H r) >> b) + p_u z_u narrowed to Q.11, clipped to
+ *                  +-beta in BOX mode; r <- r - h_u (c - z_u), each entry narrowed;
+ * where every narrowing to 16 bits rounds half up and saturates, the inner
+ * products are exact sums (the paper's 36-bit adder tree, which they fit when
+ * every sum stays within 36 bits), and R is the reciprocal unit: normalise x to
+ * [1/2, 1), index a table of round(2^18 / (1 + (i + 1/2)/2048)) with the 11 bits
+ * after the leading one, shift back to Q.11.  The shifts by b assume channel
+ * entries of unit average power (||h_u||^2 close to B): scale H and y by one
+ * factor c and N0 by c^2 to get there, which leaves OCD's estimate unchanged.
+ * The soft output is formed in FP32 from the fixed-point z and p (mu = p / 2048 in
+ * MMSE mode, 1 in BOX mode; rho = g / lambda, BOX g Es / N0), with ocd_detect's
+ * layout and sign.
+ *   pb          mode OCD_MMSE or OCD_BOX (OCD_HYBRID: OCD_EUNSUPPORTED); storage is
+ *               not used; beta <= 0 selects the constellation edge, rounded to Q.11
+ *   H, y        device int16 (re, im) pairs, [W][U][B][2] and [W][S][B][2], Q5.11
+ *   z           device int16 pairs [W][S][U][2], Q5.11, or NULL
+ *   llr         device FP32 [W][S][U][Q], or NULL (not both NULL)
+ * Asynchronous on `stream`; no allocation. */
+ocd_status ocd_detect_fixed(const ocd_problem *pb, const int16_t *H, const int16_t *y, int16_t *z,
+                            float *llr, hipStream_t stream);
 
 /* Drops every cached hipGraph and pinned staging buffer (e.g. before freeing a
  * workspace that ocd_detect_jobs captured). */

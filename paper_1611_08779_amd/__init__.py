@@ -32,8 +32,9 @@ __all__ = [
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_get_plan", "ocd_set_plan",
     "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
-    "ocd_release_graphs", "ocd_detect_mmse",
-    "problem", "detect", "preprocess", "backward", "detect_jobs", "detect_mmse", "OCD_JOBS_GRAPH",
+    "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed",
+    "problem", "detect", "preprocess", "backward", "detect_jobs", "detect_mmse", "detect_fixed",
+    "OCD_JOBS_GRAPH",
     "OCD_JOBS_TUNE",
     "OCD_JOBS_PERSISTENT", "JobsCall",
 ]
@@ -108,6 +109,7 @@ def _load():
                              ctypes.POINTER(vp), ctypes.c_int, vp, sz, ctypes.c_int, vp], ctypes.c_int),
         "ocd_release_graphs": ([], None),
         "ocd_detect_mmse": ([P, vp, vp, fp, fp, ctypes.POINTER(Plan), vp], ctypes.c_int),
+        "ocd_detect_fixed": ([P, vp, vp, vp, fp, vp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -288,6 +290,17 @@ def ocd_detect_mmse(pb: Problem, H, y, z=None, llr=None, plan=None, stream=None)
     _check("ocd_detect_mmse", st)
 
 
+def ocd_detect_fixed(pb: Problem, H, y, z=None, llr=None, stream=None) -> None:
+    dev = H.device
+    i16 = (torch.int16,)
+    st = _lib.ocd_detect_fixed(
+        ctypes.byref(pb), _dev_ptr(H, "H", i16, pb.W * pb.U * pb.B * 4),
+        _dev_ptr(y, "y", i16, pb.W * pb.S * pb.B * 4, dev),
+        _dev_ptr(z, "z", i16, pb.W * pb.S * pb.U * 4, dev),
+        _dev_ptr(llr, "llr", (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev), _stream(stream))
+    _check("ocd_detect_fixed", st)
+
+
 def _problem_array(jobs):
     arr = (Problem * len(jobs))()
     for i, pb in enumerate(jobs):
@@ -412,6 +425,22 @@ def detect_mmse(H, y, Q, N0=1.0, Es=1.0, storage="f32", want_z=True, want_llr=Tr
     if plan is not None and not isinstance(plan, Plan):
         plan = Plan(int(plan[0]), int(plan[1]), int(plan[2]) if len(plan) > 2 else 0, 0)
     ocd_detect_mmse(pb, H, y, z, llr, plan, stream)
+    return z, llr
+
+
+def detect_fixed(H, y, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, want_z=True, want_llr=True,
+                 stream=None):
+    """Runs ocd_detect_fixed on int16 Q5.11 pairs H [W,U,B,2], y [W,S,B,2]; returns
+    (z int16 [W,S,U,2], llr [W,S,U,Q]) with None for outputs not asked for."""
+    if H.dim() != 4 or y.dim() != 4 or H.shape[-1] != 2 or y.shape[-1] != 2:
+        raise ValueError("H and y must be int16 [W,U,B,2] and [W,S,B,2]")
+    W, U, B, _ = H.shape
+    S = y.shape[1]
+    pb = problem(B, U, W, S, Q, K, mode, "f32", N0, Es, beta)
+    dev = H.device
+    z = torch.empty(W, S, U, 2, device=dev, dtype=torch.int16) if want_z else None
+    llr = torch.empty(W, S, U, Q, device=dev, dtype=torch.float32) if want_llr else None
+    ocd_detect_fixed(pb, H, y, z, llr, stream)
     return z, llr
 
 

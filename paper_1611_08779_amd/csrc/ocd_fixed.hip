@@ -1,0 +1,237 @@
+// ocd_fixed.hip -- Algorithm 1 in the fixed-point datapath of Section IV-C, for
+// comparing the paper's 16-bit design with floating point on the same inputs.
+//
+// Words (H, y, the residual r, z, beta, d^-1, p) are 16-bit two's complement with
+// 11 fractional bits (Q5.11).  Products of two words are exact; the inner
+// products are exact 64-bit sums of them (the paper's 36-bit adder tree, which
+// they fit on any input whose sums stay in 36 bits).  ||h_u||^2 + alpha and
+// h_u^H r are shifted right by b = ceil(log2 B); the two shifts cancel in
+// d^-1 h^H r.  The reciprocal d^-1 comes from normalising its input to [1/2, 1),
+// indexing a 2048-entry table of 18-bit normalised reciprocals with the 11 bits
+// after the leading one, and shifting back.  Every narrowing to 16 bits rounds
+// half up and saturates.  The paper's design has no soft-output unit: the LLRs
+// are formed in FP32 from the fixed-point z and p, as in the floating-point path.
+//
+// One lane group of L lanes per vector; lane j holds residual entries
+// b = j + L i.  Integer sums are exact, so the order of the cross-lane sums does
+// not matter and the result is bit-exact.  H is read from global memory at every
+// update: the S symbols of a subcarrier read the same columns, which stay in
+// the caches.
+#include <stdint.h>
+
+#include <cmath>
+
+#include "ocd.h"
+#include "ocd_stage.h"
+
+namespace ocd {
+
+struct FxParams {
+    int B, U, W, S, K, Q, box, b;
+    long long lam_q;    // alpha in Q.22
+    int beta_fx;        // box half-width in Q.11
+    float lam, Es, N0, sqEs, qscale;
+    const int16_t *H;   // [W][U][B][2]
+    const int16_t *y;   // [W][S][B][2]
+    int16_t *z;         // [W][S][U][2] or nullptr
+    float *llr;         // [W][S][U][Q] or nullptr
+};
+
+__device__ __forceinline__ long long fx_sat16(long long v)
+{
+    return v < -32768 ? -32768 : (v > 32767 ? 32767 : v);
+}
+
+// v / 2^s rounded half up (s >= 1)
+__device__ __forceinline__ long long fx_round_shift(long long v, int s)
+{
+    return (v + (1ll << (s - 1))) >> s;
+}
+
+// Q.11 reciprocal of x > 0 given in Q.22 units: normalise, index the table with
+// the 11 bits after the leading one, denormalise; 0 for x <= 0.  The table entry
+// round(2^18 / (1 + (i + 1/2) / 2048)) is evaluated where it is needed (IEEE
+// double division is correctly rounded, so it is the table's value).
+__device__ __forceinline__ long long fx_recip(long long x)
+{
+    if (x <= 0) return 0;
+    const int n = 64 - __clzll(x);   // bit length
+    const long long idx = n >= 12 ? (x >> (n - 12)) & 2047 : (x << (12 - n)) & 2047;
+    const long long lut = (long long)floor(262144.0 / (1.0 + ((double)idx + 0.5) / 2048.0) + 0.5);
+    const long long d = (16 - n >= 0) ? lut * (1ll << (16 - n)) : fx_round_shift(lut, n - 16);
+    return fx_sat16(d);
+}
+
+template <int L>
+__device__ __forceinline__ long long group_sum_i64(long long x)
+{
+#pragma unroll
+    for (int off = L / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, L);
+    return x;
+}
+
+template <int L, int NPL>
+__global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
+{
+    constexpr int G = 256 / L;
+    __shared__ int zs[G][32][2];
+    __shared__ int ds[G][32], ps[G][32];
+    __shared__ long long gs[G][32];
+    const int grp = threadIdx.x / L, j = threadIdx.x % L;
+    const long v = (long)blockIdx.x * G + grp;
+    if (v >= (long)P.W * P.S) return;   // a whole lane group at once
+    const int U = P.U, B = P.B, b = P.b;
+    const int16_t *Hw = P.H + (size_t)(v / P.S) * U * B * 2;
+    const int16_t *yv = P.y + (size_t)v * B * 2;
+
+    int rr[NPL], ri[NPL];   // residual entries j + L i, Q.11
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+        const int a = j + L * i;
+        rr[i] = a < B ? yv[2 * a] : 0;
+        ri[i] = a < B ? yv[2 * a + 1] : 0;
+    }
+
+    // preprocessing (Alg. 1, initialisation): ||h_u||^2, d_u^-1, p_u
+    for (int u = 0; u < U; ++u) {
+        const int16_t *hu = Hw + (size_t)u * B * 2;
+        long long g = 0;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int a = j + L * i;
+            if (a < B) {
+                const long long hr = hu[2 * a], hi = hu[2 * a + 1];
+                g += hr * hr + hi * hi;
+            }
+        }
+        g = group_sum_i64<L>(g);
+        if (j == 0) {
+            const long long d = fx_recip((g + P.lam_q) >> b);
+            gs[grp][u] = g;
+            ds[grp][u] = (int)d;
+            ps[grp][u] = (int)fx_sat16(fx_round_shift(d * (g >> b), 22));
+            zs[grp][u][0] = 0;
+            zs[grp][u][1] = 0;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    for (int k = 0; k < P.K; ++k)
+        for (int u = 0; u < U; ++u) {
+            const int16_t *hu = Hw + (size_t)u * B * 2;
+            int hr[NPL], hi[NPL];
+            long long ire = 0, iim = 0;   // h_u^H r, Q.22
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                const int a = j + L * i;
+                hr[i] = a < B ? hu[2 * a] : 0;
+                hi[i] = a < B ? hu[2 * a + 1] : 0;
+                ire += (long long)hr[i] * rr[i] + (long long)hi[i] * ri[i];
+                iim += (long long)hr[i] * ri[i] - (long long)hi[i] * rr[i];
+            }
+            ire = group_sum_i64<L>(ire) >> b;
+            iim = group_sum_i64<L>(iim) >> b;
+            const long long d = ds[grp][u], p = ps[grp][u];
+            const long long zr = zs[grp][u][0], zi = zs[grp][u][1];
+            // c = d^-1 h^H r + p z in Q.33, narrowed to Q.11
+            long long cre = fx_sat16(fx_round_shift(d * ire + p * zr * 2048, 22));
+            long long cim = fx_sat16(fx_round_shift(d * iim + p * zi * 2048, 22));
+            if (P.box) {
+                cre = cre > P.beta_fx ? P.beta_fx : (cre < -P.beta_fx ? -P.beta_fx : cre);
+                cim = cim > P.beta_fx ? P.beta_fx : (cim < -P.beta_fx ? -P.beta_fx : cim);
+            }
+            const long long dre = cre - zr, dim = cim - zi;
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                rr[i] = (int)fx_sat16(rr[i] - fx_round_shift(hr[i] * dre - hi[i] * dim, 11));
+                ri[i] = (int)fx_sat16(ri[i] - fx_round_shift(hr[i] * dim + hi[i] * dre, 11));
+            }
+            __builtin_amdgcn_wave_barrier();   // every lane has read z_u
+            if (j == 0) {
+                zs[grp][u][0] = (int)cre;
+                zs[grp][u][1] = (int)cim;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+
+    // outputs: lane pair index idx = 2u + axis
+    const int Q = P.Q, half = Q >> 1;
+    for (int idx = j; idx < 2 * U; idx += L) {
+        const int u = idx >> 1, ax = idx & 1;
+        const int zv = zs[grp][u][ax];
+        if (P.z) P.z[(size_t)v * U * 2 + idx] = (int16_t)zv;
+        if (P.llr) {
+            const float g = (float)gs[grp][u] * (1.0f / 4194304.0f);
+            float mu, rho;
+            if (P.lam > 0.f) {
+                mu = (float)ps[grp][u] * (1.0f / 2048.0f);
+                rho = g / P.lam;
+            } else {
+                mu = 1.0f;
+                rho = g * P.Es / P.N0;
+            }
+            float a = 0.f, c = 0.f;
+            if (mu > 0.f && rho > 0.f) {
+                a = 1.0f / (mu * P.sqEs * P.qscale);
+                c = rho * P.qscale * P.qscale;
+            }
+            const float t = (float)zv * (1.0f / 2048.0f) * a;
+            float *dst = P.llr + ((size_t)v * U + u) * Q + ax * half;
+            if (half == 3) axis_llrs<3>(t, c, dst);
+            else if (half == 2) axis_llrs<2>(t, c, dst);
+            else axis_llrs<1>(t, c, dst);
+        }
+    }
+}
+
+template <int L, int NPL>
+static hipError_t launch_fx_t(const FxParams &p, hipStream_t s)
+{
+    constexpr int G = 256 / L;
+    const long nvec = (long)p.W * p.S;
+    hipLaunchKernelGGL((k_forward_fx<L, NPL>), dim3((unsigned)((nvec + G - 1) / G)), dim3(256), 0,
+                       s, p);
+    return hipGetLastError();
+}
+
+static hipError_t launch_fx(const FxParams &p, hipStream_t s)
+{
+    if (p.B <= 32) return launch_fx_t<16, 2>(p, s);
+    if (p.B <= 64) return launch_fx_t<16, 4>(p, s);
+    if (p.B <= 128) return launch_fx_t<16, 8>(p, s);
+    if (p.B <= 256) return launch_fx_t<16, 16>(p, s);
+    if (p.B <= 512) return launch_fx_t<32, 16>(p, s);
+    return launch_fx_t<32, 32>(p, s);
+}
+
+ocd_status validate(const ocd_problem *pb);
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_detect_fixed(const ocd_problem *pb, const int16_t *H, const int16_t *y,
+                                       int16_t *z, float *llr, hipStream_t stream)
+{
+    using namespace ocd;
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!H || !y || (!z && !llr)) return OCD_EINVAL;
+    if (pb->mode == OCD_HYBRID) return OCD_EUNSUPPORTED;
+    if (pb->W == 0) return OCD_OK;
+    FxParams P;
+    P.B = pb->B; P.U = pb->U; P.W = pb->W; P.S = pb->S; P.K = pb->K; P.Q = pb->Q;
+    P.box = pb->mode == OCD_BOX;
+    P.b = 0;
+    while ((1 << P.b) < pb->B) ++P.b;
+    const double lam = pb->mode == OCD_MMSE ? (double)pb->N0 / (double)pb->Es : 0.0;
+    P.lam_q = (long long)std::floor(lam * 4194304.0 + 0.5);
+    const int M = 1 << (pb->Q / 2);
+    const double edge = (double)(M - 1) / std::sqrt(2.0 * (double)(M * M - 1) / 3.0);
+    const double beta = pb->beta > 0.f ? (double)pb->beta : edge * std::sqrt((double)pb->Es);
+    P.beta_fx = (int)std::floor(beta * 2048.0 + 0.5);
+    P.lam = (float)lam;
+    P.Es = pb->Es; P.N0 = pb->N0;
+    P.sqEs = std::sqrt(pb->Es);
+    P.qscale = qam_scale(pb->Q);
+    P.H = H; P.y = y; P.z = z; P.llr = llr;
+    return launch_fx(P, stream) == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}

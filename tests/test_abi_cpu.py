@@ -212,3 +212,21 @@ def test_mmse_heuristic_plan_fits(lib, B, U, S):
     d = ctypes.c_void_p(0x1000)
     pb = Problem(**{**_good(), "B": B, "U": U, "S": S, "W": 0})
     assert lib.ocd_detect_mmse(ctypes.byref(pb), d, d, d, d, None, None) == 0
+
+
+def test_fixed_point_detector_checks_its_arguments_on_the_host(lib):
+    lib.ocd_detect_fixed.restype = ctypes.c_int
+    lib.ocd_detect_fixed.argtypes = [ctypes.POINTER(Problem)] + [ctypes.c_void_p] * 5
+    d = ctypes.c_void_p(0x1000)
+
+    def call(over=None, H=d, y=d, z=d, llr=d):
+        pb = Problem(**{**_good(), **(over or {})})
+        return lib.ocd_detect_fixed(ctypes.byref(pb), H, y, z, llr, None)
+
+    assert call(H=None) == -1
+    assert call(y=None) == -1
+    assert call(z=None, llr=None) == -1
+    assert call(dict(Q=5)) == -1
+    assert call(dict(mode=2)) == -2      # HYBRID: per-sweep regularisers are not in the design
+    assert call(dict(W=0)) == 0
+    assert call(dict(W=0, mode=1)) == 0
