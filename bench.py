@@ -14,8 +14,9 @@ on its stream.
 One JSON line goes to stdout; progress goes to stderr.  Besides the contract's
 fields it carries the roofline of the dominant kernel, the FP64 oracle timed on
 this host's cores, and the other forms: FP16 storage (speedup at equal BER),
-the S=1 variant (one H per vector, HBM-bound), explicit MMSE detection (the
-detector OCD approximates, at paired bit errors), 48 uneven jobs in one persistent
+the S=1 variant (one H per vector, HBM-bound), the paper's 16-bit fixed-point
+datapath, explicit MMSE detection (the detector OCD approximates, at paired bit
+errors), 48 uneven jobs in one persistent
 graph launch against one launch per job, and the forward+backward step of the
 differentiable form in vectors/s.
 
@@ -454,6 +455,35 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def fixed_form(torch, ocd, dev, args, slots, pb32, t_ocd, errs_ocd, nbits):
+    """OCD in the paper's 16-bit fixed-point datapath on the headline slots, its
+    inputs quantised to Q5.11 at the unit-power channel scale (H, y times sqrt(B),
+    N0 times B: the same OCD estimate); bit errors paired with the FP32 path's."""
+    log("form: fixed-point datapath")
+    B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
+    c = math.sqrt(B) * 2048.0
+
+    def q(t):
+        v = torch.view_as_real(t).to(torch.float64) * c
+        return torch.clamp(torch.floor(v + 0.5), -32768, 32767).to(torch.int16).contiguous()
+
+    N0 = float(torch.tensor(pb32.N0 * B, dtype=torch.float32))
+    pbf = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
+    ins = [{"H": q(sl["H"]), "y": q(sl["y"])} for sl in slots]
+    outs = [(torch.empty(W, S, U, 2, dtype=torch.int16, device=dev),
+             torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
+    fns = [(lambda i=i: ocd.ocd_detect_fixed(pbf, ins[i]["H"], ins[i]["y"], outs[i][0],
+                                             outs[i][1])) for i in range(len(slots))]
+    tk = kernel_durations(torch, fns)
+    t, _ = time_graph(torch, GraphedSteps(torch, fns), max(200, args.steps // 4), 20)
+    errs = sum(int(((outs[i][1] > 0).to(torch.uint8) != slots[i]["bits"]).sum().item())
+               for i in range(len(slots)))
+    return {"gbps": W * S * U * Q / t / 1e9, "ms_per_step": t * 1e3, "avg_kernel_us": tk * 1e6,
+            "slowdown_vs_fp32": t / t_ocd, "bit_errors_fixed": errs, "bit_errors_fp32": errs_ocd,
+            "bits": nbits, "kernel": "ocd::k_forward_fx<16, 8>",
+            "inputs": "Q5.11 int16 pairs of sqrt(B) H and sqrt(B) y, N0 B"}
+
+
 def mmse_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, errs_ocd, nbits):
     """Explicit MMSE detection on the headline slots: a small plan search on the
     first slot, then the same graph-replayed timing as the headline; bit errors
@@ -556,6 +586,9 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
         "hbm_frac": bytes16 * W * S / t16 / 1e9 / HBM_PEAK_GBPS,
     }
     del s16, o16
+
+    # ---- the fixed-point datapath of Section IV-C on the same slots
+    forms["fixed_point_q11"] = fixed_form(torch, ocd, dev, args, slots, pb32, t32, e32, nb)
 
     # ---- explicit MMSE (Sections II-B, II-E): the detector OCD approximates
     forms["exact_mmse"] = mmse_form(torch, ocd, synth, dev, args, slots, pb32, t32, e32, nb)

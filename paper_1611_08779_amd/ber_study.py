@@ -31,7 +31,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 DETECTORS = ([("ocd-mmse", k) for k in (1, 2, 3, 4)] + [("ocd-box", k) for k in (1, 2, 3, 4)]
-             + [("mmse", 0)])
+             + [("mmse", 0)] + [("ocd-box-fx", k) for k in (3, 4)])
+
+
+def quantize_q11(t, scale):
+    """complex64 device tensor -> int16 (re, im) pairs in Q5.11 of t * scale, rounded
+    half up and saturated (the fixed-point detector's input format)."""
+    import torch
+    v = torch.view_as_real(t).to(torch.float64) * (scale * 2048.0)
+    return torch.clamp(torch.floor(v + 0.5), -32768, 32767).to(torch.int16).contiguous()
 
 
 def snr_for_ebn0(ebn0_db: float, B: int, U: int, Q: int) -> float:
@@ -45,6 +53,14 @@ def count_errors(ocd, torch, wl, Q, K, det):
     N0 = float(wl["N0"])
     if det == "mmse":
         _, L = ocd.detect_mmse(wl["H"], wl["y"], Q, N0, want_z=False)
+    elif det.endswith("-fx"):
+        # the datapath's shifts assume unit-power channel entries: H, y times sqrt(B)
+        # and N0 times B, which leaves OCD's estimate unchanged
+        B = wl["H"].shape[-1]
+        c = math.sqrt(B)
+        mode = "box" if det.startswith("ocd-box") else "mmse"
+        _, L = ocd.detect_fixed(quantize_q11(wl["H"], c), quantize_q11(wl["y"], c), K, Q, mode,
+                                float(torch.tensor(N0 * B, dtype=torch.float32)), want_z=False)
     else:
         mode = "mmse" if det == "ocd-mmse" else "box"
         _, L, _ = ocd.detect(wl["H"], wl["y"], K, Q, mode, N0, want_z=False)
@@ -80,8 +96,28 @@ def study(antennas, ebn0s, slots, U=8, Q=6, W=1200, S=14, seed=9000, log=None):
     return out
 
 
+def ebn0_at(res, B, ebn0s, key, target):
+    """Eb/N0 (dB) where the BER of detector `key` crosses `target`, by linear
+    interpolation of log10(BER) between the two sweep points around it; None if
+    the sweep does not cross it."""
+    pts = [(eb, res[(B, eb)][key] / res[(B, eb)]["bits"]) for eb in ebn0s]
+    for (e0, b0), (e1, b1) in zip(pts, pts[1:]):
+        if b0 >= target > b1 and b1 > 0:
+            l0, l1, lt = math.log10(b0), math.log10(b1), math.log10(target)
+            return e0 + (e1 - e0) * (l0 - lt) / (l0 - l1)
+    return None
+
+
+def fixed_point_loss(res, B, ebn0s, K, target):
+    """SNR loss (dB) of the fixed-point OCD-BOX against the floating-point one at a BER."""
+    a = ebn0_at(res, B, ebn0s, "ocd-box/%d" % K, target)
+    b = ebn0_at(res, B, ebn0s, "ocd-box-fx/%d" % K, target)
+    return None if a is None or b is None else b - a
+
+
 def table(res, B, ebn0s):
-    keys = ["%s/%d" % d for d in DETECTORS if d[0] != "mmse"] + ["mmse"]
+    keys = ["%s/%d" % d for d in DETECTORS if d[0] != "mmse"]
+    keys = keys[:8] + ["mmse"] + keys[8:]
     lines = ["| Eb/N0 (dB) | " + " | ".join(keys) + " |",
              "|---" * (len(keys) + 1) + "|"]
     for eb in ebn0s:
@@ -109,6 +145,11 @@ def main():
         print("\nB = %d, U = 8, 64-QAM, %d slots of 1200 x 14 vectors (%d bits per point)\n"
               % (B, a.slots, res[(B, ebn0s[0])]["bits"]))
         print(table(res, B, ebn0s))
+        for K in (3, 4):
+            for target in (1e-2, 1e-3):
+                loss = fixed_point_loss(res, B, ebn0s, K, target)
+                print("\nfixed-point OCD-BOX K=%d, loss at BER %.0e: %s" % (
+                    K, target, "%.3f dB" % loss if loss is not None else "not crossed"))
     if a.out:
         with open(a.out, "w") as fh:
             json.dump([{"B": B, "ebn0_db": eb, **r} for (B, eb), r in sorted(res.items())], fh,

@@ -62,11 +62,25 @@ __device__ __forceinline__ long long fx_recip(long long x)
     return fx_sat16(d);
 }
 
+// A 64-bit lane value from another lane of the row: the DPP move of both halves.
+template <int CTRL>
+__device__ __forceinline__ long long dpp_get_i64(long long x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Exact sum over the L lanes of an aligned group (L = 16 or 32), the same in
+// every lane; integer addition is associative, so the order does not matter.
 template <int L>
 __device__ __forceinline__ long long group_sum_i64(long long x)
 {
-#pragma unroll
-    for (int off = L / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, L);
+    x += dpp_get_i64<DPP_QUAD_XOR1>(x);
+    x += dpp_get_i64<DPP_QUAD_XOR2>(x);
+    x += dpp_get_i64<DPP_ROW_HALF_MIRROR>(x);
+    x += dpp_get_i64<DPP_ROW_MIRROR>(x);
+    if constexpr (L >= 32) x += __shfl_xor(x, 16, 32);
     return x;
 }
 
@@ -116,16 +130,30 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
     }
     __builtin_amdgcn_wave_barrier();
 
+    // column entries as (re, im) int16 pairs in one dword; lanes past B hold 0
+    auto load_col = [&](int u, uint32_t (&h)[NPL]) {
+        const uint32_t *hu = reinterpret_cast<const uint32_t *>(Hw) + (size_t)u * B;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int a = j + L * i;
+            h[i] = a < B ? hu[a] : 0u;
+        }
+    };
+    uint32_t hn[NPL];
+    load_col(0, hn);
     for (int k = 0; k < P.K; ++k)
         for (int u = 0; u < U; ++u) {
-            const int16_t *hu = Hw + (size_t)u * B * 2;
             int hr[NPL], hi[NPL];
+#pragma unroll
+            for (int i = 0; i < NPL; ++i) {
+                hr[i] = (int)(int16_t)(hn[i] & 0xFFFFu);
+                hi[i] = (int)(int16_t)(hn[i] >> 16);
+            }
+            // the next update's column is in flight while this one computes
+            load_col(u + 1 < U ? u + 1 : 0, hn);
             long long ire = 0, iim = 0;   // h_u^H r, Q.22
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-                const int a = j + L * i;
-                hr[i] = a < B ? hu[2 * a] : 0;
-                hi[i] = a < B ? hu[2 * a + 1] : 0;
                 ire += (long long)hr[i] * rr[i] + (long long)hi[i] * ri[i];
                 iim += (long long)hr[i] * ri[i] - (long long)hi[i] * rr[i];
             }

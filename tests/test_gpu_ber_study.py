@@ -25,8 +25,15 @@ def test_study_counts_match_the_oracle():
     bits = wl["bits"].cpu().numpy()
     N0 = float(np.float32(wl["N0"]))
     assert res["bits"] == bits.size
+    c = np.sqrt(B)
+    Hq = bs.quantize_q11(wl["H"], c).cpu().numpy()
+    yq = bs.quantize_q11(wl["y"], c).cpu().numpy()
     for det, K in bs.DETECTORS:
-        if det == "mmse":
+        if det.endswith("-fx"):
+            N0f = float(np.float32(float(np.float32(wl["N0"])) * B))   # as the study forms it
+            _, L = oracle.ocd_fixed(Hq, yq, K, Q, "box", N0=N0f, threads=0)
+            key = "%s/%d" % (det, K)
+        elif det == "mmse":
             _, L, _ = oracle.mmse(H, y, Q, N0=N0, threads=0)
             key = "mmse"
         else:
