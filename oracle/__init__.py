@@ -268,3 +268,19 @@ def ocd_fixed(Hq, yq, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, threads=1):
 def fx_recip(x):
     """The fixed-point reciprocal unit (reading F5): Q.22 integer x -> Q.11 integer."""
     return int(_load().oracle_fx_recip(int(x)))
+
+
+def ofdm_demodulate(x, N, Ncp, W):
+    """OFDM demodulation at the base station (Section II-A): per antenna b and
+    symbol s, drop the first Ncp samples (the cyclic prefix), take the unitary
+    N-point DFT X[k] = N^-1/2 sum_n x[Ncp + n] exp(-2 pi i k n / N) (numpy's FFT in
+    FP64 as the DFT), and keep the W used bins -W/2 .. -1, +1 .. +W/2 (DC empty) in
+    increasing frequency.  x [B][S][Ncp + N] -> y [W][S][B] complex128."""
+    x = np.asarray(x, np.complex128)
+    if W % 2 or W // 2 >= N // 2 or x.shape[-1] != Ncp + N:
+        raise ValueError("bad OFDM shape")
+    X = np.fft.fft(x[..., Ncp:Ncp + N], axis=-1, norm="ortho")
+    kneg = np.arange(N - W // 2, N)          # -W/2 .. -1
+    kpos = np.arange(1, W // 2 + 1)          # +1 .. +W/2
+    Y = X[..., np.concatenate([kneg, kpos])]  # [B][S][W]
+    return np.ascontiguousarray(np.transpose(Y, (2, 1, 0)))

@@ -50,6 +50,9 @@ __all__ = [
     "rayleigh_channel",
     "make_workload",
     "batched_job_list",
+    "ofdm_used_bins",
+    "ofdm_time_domain",
+    "ofdm_time_domain_device",
 ]
 
 
@@ -183,3 +186,43 @@ def make_workload_device(B: int, U: int, W: int, S: int, Q: int, snr_db: float, 
     s = math.sqrt(Es) * torch.complex(amp[lvl[lab_i]], amp[lvl[lab_q]])        # [W,S,U]
     y = torch.matmul(s, H.contiguous()) + cn((W, S, B), math.sqrt(0.5 * N0))     # [W,S,B]
     return {"H": H.contiguous(), "y": y.contiguous(), "bits": bits, "N0": N0, "Es": float(Es)}
+
+
+# ---------------------------------------------------------------- OFDM transmitter side
+
+def ofdm_used_bins(N: int, W: int) -> np.ndarray:
+    """DFT bin that carries subcarrier w (the transmitter's mapping, LTE style):
+    the W/2 lowest subcarriers on the negative frequencies -W/2 .. -1 (bins
+    N - W/2 .. N - 1), the others on +1 .. +W/2; DC is left empty."""
+    if W % 2 or W // 2 >= N // 2:
+        raise ValueError("W must be even and below N - 1")
+    w = np.arange(W)
+    return np.where(w < W // 2, N - W // 2 + w, w - W // 2 + 1)
+
+
+def ofdm_time_domain(y: np.ndarray, N: int, Ncp: int) -> np.ndarray:
+    """Receive antennas' time-domain samples whose OFDM demodulation is ``y``.
+
+    ``y`` [W][S][B] (frequency domain, the detector's layout) -> ``x``
+    [B][S][Ncp + N] complex128: per antenna and symbol the W values are placed on
+    their bins (zeros elsewhere), transformed by the unitary inverse DFT, and the
+    last Ncp samples are prepended as the cyclic prefix (Section II-A: with a
+    cyclic prefix at least as long as the channel, this is the same model)."""
+    W, S, B = y.shape
+    full = np.zeros((B, S, N), np.complex128)
+    full[:, :, ofdm_used_bins(N, W)] = np.transpose(np.asarray(y, np.complex128), (2, 1, 0))
+    sym = np.fft.ifft(full, axis=-1) * math.sqrt(N)
+    return np.concatenate([sym[..., N - Ncp:], sym], axis=-1)
+
+
+def ofdm_time_domain_device(y, N: int, Ncp: int):
+    """:func:`ofdm_time_domain` with torch on the device: complex64 [W][S][B] ->
+    complex64 [B][S][Ncp + N] (the inverse DFT in complex64)."""
+    import torch
+
+    W, S, B = y.shape
+    full = torch.zeros((B, S, N), dtype=torch.complex64, device=y.device)
+    bins = torch.as_tensor(ofdm_used_bins(N, W), device=y.device)
+    full[:, :, bins] = y.permute(2, 1, 0)
+    sym = torch.fft.ifft(full, dim=-1) * math.sqrt(N)
+    return torch.cat([sym[..., N - Ncp:], sym], dim=-1).contiguous()
