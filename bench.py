@@ -14,8 +14,8 @@ on its stream.
 One JSON line goes to stdout; progress goes to stderr.  Besides the contract's
 fields it carries the roofline of the dominant kernel, the FP64 oracle timed on
 this host's cores, and the other forms: FP16 storage (speedup at equal BER),
-the S=1 variant (one H per vector, HBM-bound), the paper's 16-bit fixed-point
-datapath, explicit MMSE detection (the detector OCD approximates, at paired bit
+the S=1 variant (one H per vector, HBM-bound), the OFDM front end (alone and
+followed by detection), the paper's 16-bit fixed-point datapath, explicit MMSE detection (the detector OCD approximates, at paired bit
 errors), 48 uneven jobs in one persistent
 graph launch against one launch per job, and the forward+backward step of the
 differentiable form in vectors/s.
@@ -455,6 +455,40 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def ofdm_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, N=2048, Ncp=144):
+    """The OFDM front end on the headline slots: time-domain slots (per antenna and
+    symbol, a 144-sample cyclic prefix and 2048 samples) built from the slots'
+    frequency-domain vectors, demodulated into the detector's layout; timed alone
+    (HBM roofline: every sample read once, every used bin written once) and
+    followed by detection."""
+    log("form: OFDM front end")
+    B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
+    xs = [synth.ofdm_time_domain_device(sl["y"], N, Ncp) for sl in slots[:8]]
+    ys = [torch.empty(W, S, B, dtype=torch.complex64, device=dev) for _ in xs]
+    sh = ocd.OfdmShape(B, S, N, Ncp, W)
+    fns = [(lambda i=i: ocd.ocd_ofdm_demodulate(sh, xs[i], ys[i])) for i in range(len(xs))]
+    tk = kernel_durations(torch, fns)
+    t, _ = time_graph(torch, GraphedSteps(torch, fns), max(200, args.steps // 4), 20)
+    err = float(torch.max(torch.abs(ys[0] - slots[0]["y"])).item() /
+                torch.max(torch.abs(slots[0]["y"])).item())
+    outs = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
+             torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in xs]
+
+    def both(i):
+        ocd.ocd_ofdm_demodulate(sh, xs[i], ys[i])
+        ocd.ocd_detect(pb32, slots[i]["H"], ys[i], z=outs[i][0], llr=outs[i][1])
+    t2, _ = time_graph(torch, GraphedSteps(torch, [(lambda i=i: both(i)) for i in range(len(xs))]),
+                       max(200, args.steps // 4), 20)
+    nbytes = B * S * (N + Ncp) * 8 + W * S * B * 8
+    return {"us_per_slot": t * 1e6, "avg_kernel_us": tk * 1e6,
+            "hbm_GBps": nbytes / t / 1e9, "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBPS,
+            "bytes_per_slot": nbytes, "max_rel_dev_from_model": err,
+            "front_end_plus_ocd_us_per_slot": t2 * 1e6,
+            "front_end_plus_ocd_gbps": W * S * U * Q / t2 / 1e9,
+            "ocd_alone_us_per_slot": t_ocd * 1e6,
+            "kernel": "ocd::k_ofdm_fft<2048>", "shape": "N=2048, CP=144, W=1200, B=128, S=14"}
+
+
 def fixed_form(torch, ocd, dev, args, slots, pb32, t_ocd, errs_ocd, nbits):
     """OCD in the paper's 16-bit fixed-point datapath on the headline slots, its
     inputs quantised to Q5.11 at the unit-power channel scale (H, y times sqrt(B),
@@ -589,6 +623,9 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
 
     # ---- the fixed-point datapath of Section IV-C on the same slots
     forms["fixed_point_q11"] = fixed_form(torch, ocd, dev, args, slots, pb32, t32, e32, nb)
+
+    # ---- OFDM front end (Section II-A) feeding the detector
+    forms["ofdm_front_end"] = ofdm_form(torch, ocd, synth, dev, args, slots, pb32, t32)
 
     # ---- explicit MMSE (Sections II-B, II-E): the detector OCD approximates
     forms["exact_mmse"] = mmse_form(torch, ocd, synth, dev, args, slots, pb32, t32, e32, nb)

@@ -269,6 +269,29 @@ ocd_status ocd_detect_mmse(const ocd_problem *pb, const void *H, const void *y, 
 ocd_status ocd_detect_fixed(const ocd_problem *pb, const int16_t *H, const int16_t *y, int16_t *z,
                             float *llr, hipStream_t stream);
 
+/* OFDM demodulation at the base station, the step before detection (Section II-A:
+ * after the cyclic prefixes are removed, the time-domain samples of every antenna
+ * are transformed back to the frequency domain by a DFT).  For every antenna b
+ * and OFDM symbol s:
+ *   X[k] = N^-1/2 sum_{n<N} x[b][s][Ncp + n] exp(-2 pi i k n / N)   (unitary DFT)
+ *   y[w][s][b] = X[k_w],  k_w = N - W/2 + w for w < W/2 (frequencies -W/2 .. -1),
+ *                         k_w = w - W/2 + 1 otherwise (+1 .. +W/2); DC is not used,
+ * i.e. y is the detector's receive-vector layout [W][S][B] for ocd_detect.
+ *   sh       N in {256, 512, 1024, 2048, 4096}; 0 <= Ncp <= N; W even, 2 <= W and
+ *            W/2 < N/2; B, S >= 1 (else OCD_EINVAL)
+ *   x        device [B][S][Ncp + N] complex FP32 (interleaved), each symbol's cyclic
+ *            prefix first
+ *   y        device [W][S][B] complex FP32, overwritten
+ * FP32 arithmetic (Stockham FFT, twiddles rounded from double).  Asynchronous on
+ * `stream`; no allocation. */
+typedef struct {
+    int B, S;   /* receive antennas, OFDM symbols */
+    int N, Ncp; /* DFT size and cyclic-prefix length in samples */
+    int W;      /* used subcarriers */
+} ocd_ofdm_shape;
+ocd_status ocd_ofdm_demodulate(const ocd_ofdm_shape *sh, const float *x, float *y,
+                               hipStream_t stream);
+
 /* Drops every cached hipGraph and pinned staging buffer (e.g. before freeing a
  * workspace that ocd_detect_jobs captured). */
 void ocd_release_graphs(void);

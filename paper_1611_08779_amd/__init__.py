@@ -32,7 +32,8 @@ __all__ = [
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_get_plan", "ocd_set_plan",
     "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
-    "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed",
+    "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed", "ocd_ofdm_demodulate",
+    "OfdmShape", "ofdm_demodulate",
     "problem", "detect", "preprocess", "backward", "detect_jobs", "detect_mmse", "detect_fixed",
     "OCD_JOBS_GRAPH",
     "OCD_JOBS_TUNE",
@@ -79,6 +80,12 @@ class Plan(ctypes.Structure):
                 "channel_in_registers": self.channel_in_registers}
 
 
+class OfdmShape(ctypes.Structure):
+    """Mirror of ocd_ofdm_shape."""
+    _fields_ = [("B", ctypes.c_int), ("S", ctypes.c_int), ("N", ctypes.c_int),
+                ("Ncp", ctypes.c_int), ("W", ctypes.c_int)]
+
+
 class OCDError(RuntimeError):
     def __init__(self, fn, status):
         super().__init__("%s failed: %s" % (fn, _STATUS.get(status, status)))
@@ -110,6 +117,7 @@ def _load():
         "ocd_release_graphs": ([], None),
         "ocd_detect_mmse": ([P, vp, vp, fp, fp, ctypes.POINTER(Plan), vp], ctypes.c_int),
         "ocd_detect_fixed": ([P, vp, vp, vp, fp, vp], ctypes.c_int),
+        "ocd_ofdm_demodulate": ([ctypes.POINTER(OfdmShape), vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -301,6 +309,14 @@ def ocd_detect_fixed(pb: Problem, H, y, z=None, llr=None, stream=None) -> None:
     _check("ocd_detect_fixed", st)
 
 
+def ocd_ofdm_demodulate(sh: OfdmShape, x, y, stream=None) -> None:
+    c = (torch.complex64, torch.float32)
+    st = _lib.ocd_ofdm_demodulate(
+        ctypes.byref(sh), _dev_ptr(x, "x", c, sh.B * sh.S * (sh.Ncp + sh.N) * 8),
+        _dev_ptr(y, "y", c, sh.W * sh.S * sh.B * 8, x.device), _stream(stream))
+    _check("ocd_ofdm_demodulate", st)
+
+
 def _problem_array(jobs):
     arr = (Problem * len(jobs))()
     for i, pb in enumerate(jobs):
@@ -442,6 +458,17 @@ def detect_fixed(H, y, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, want_z=True,
     llr = torch.empty(W, S, U, Q, device=dev, dtype=torch.float32) if want_llr else None
     ocd_detect_fixed(pb, H, y, z, llr, stream)
     return z, llr
+
+
+def ofdm_demodulate(x, N, Ncp, W, stream=None):
+    """Runs ocd_ofdm_demodulate: time-domain x complex64 [B,S,Ncp+N] -> y complex64
+    [W,S,B], the detector's receive-vector layout."""
+    if x.dim() != 3 or x.shape[-1] != Ncp + N:
+        raise ValueError("x must be [B, S, Ncp + N]")
+    B, S, _ = x.shape
+    y = torch.empty(W, S, B, device=x.device, dtype=torch.complex64)
+    ocd_ofdm_demodulate(OfdmShape(B, S, N, Ncp, W), x, y, stream)
+    return y
 
 
 def detect_jobs(jobs, H, y, flags=0, workspace=None, stream=None):

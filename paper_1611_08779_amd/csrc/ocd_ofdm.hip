@@ -1,0 +1,272 @@
+// ocd_ofdm.hip -- OFDM demodulation at the base station, the step before
+// detection (Section II-A): per receive antenna and OFDM symbol, drop the cyclic
+// prefix, take the unitary N-point DFT, and keep the W used subcarriers (bins
+// -W/2 .. -1 and +1 .. +W/2, DC empty), written straight into the detector's
+// [W][S][B] layout.
+//
+// One FFT per N/8 threads (several FFTs per workgroup for small N), Stockham
+// auto-sort passes of radix 8 (then one of radix 4 or 2 when log2 N is not a
+// multiple of 3).  Pass with stride Ns and radix R, butterfly j:
+//   k = j mod Ns,  v_r = in[j + r N/R] * w^(r k), w = exp(-2 pi i / (Ns R)),
+//   out[(j / Ns) Ns R + k + q Ns] = sum_r v_r exp(-2 pi i r q / R).
+// The first pass reads its operands straight from HBM (in[t + r N/8] is the
+// time-domain symbol after the prefix); the last one writes the used bins
+// straight to y; the passes in between exchange through LDS.  Twiddles come from
+// a 4096-entry table of exp(-2 pi i m / 4096), built at compile time in double
+// precision and rounded to FP32.
+//
+// Each FFT writes W scattered 8-byte values (consecutive subcarriers are S B
+// entries apart in y); the FFTs of neighbouring antennas of one symbol fill the
+// rest of those cache lines.  Workgroups are mapped so that consecutive FFTs (same
+// symbol, consecutive antennas) run on the same XCD, whose L2 merges the partial
+// lines before they reach HBM.
+#include <cmath>
+
+#include "ocd.h"
+#include "ocd_device.h"
+
+namespace ocd {
+
+// ------------------------------------------------------------------ twiddle table
+
+constexpr int TW_N = 4096;
+constexpr double TW_PI = 3.14159265358979323846264338327950288;
+
+// Taylor series of sin and cos about 0, for |x| <= pi (20 terms: the first
+// neglected term is below 1e-24)
+constexpr double ct_sin(double x)
+{
+    double term = x, sum = x;
+    for (int i = 1; i < 20; ++i) {
+        term *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+
+constexpr double ct_cos(double x)
+{
+    double term = 1.0, sum = 1.0;
+    for (int i = 1; i < 20; ++i) {
+        term *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+        sum += term;
+    }
+    return sum;
+}
+
+struct TwTable {
+    float re[TW_N], im[TW_N];
+};
+
+// exp(-2 pi i m / 4096), the angle taken in (-pi, pi]
+constexpr TwTable make_twiddles()
+{
+    TwTable t{};
+    for (int m = 0; m < TW_N; ++m) {
+        const int mm = m <= TW_N / 2 ? m : m - TW_N;
+        const double a = 2.0 * TW_PI * (double)mm / (double)TW_N;
+        t.re[m] = (float)ct_cos(a);
+        t.im[m] = (float)-ct_sin(a);
+    }
+    return t;
+}
+
+__device__ const TwTable g_twiddle = make_twiddles();
+
+template <int N>
+__device__ __forceinline__ float2 twiddle(int m)   // exp(-2 pi i m / N), 0 <= m < N
+{
+    const int i = m * (TW_N / N);
+    return make_float2(g_twiddle.re[i], g_twiddle.im[i]);
+}
+
+// ------------------------------------------------------------------ small DFTs
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 mul_neg_i(float2 a) { return make_float2(a.y, -a.x); }
+
+// forward DFT of 4 points: X_q = sum_r x_r exp(-2 pi i r q / 4)
+__device__ __forceinline__ void dft4(float2 &a, float2 &b, float2 &c, float2 &d)
+{
+    const float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = mul_neg_i(csub(b, d));
+    a = cadd(t0, t2);
+    c = csub(t0, t2);
+    b = cadd(t1, t3);
+    d = csub(t1, t3);
+}
+
+// forward DFT of 8 points: two DFTs of 4 (even, odd inputs) and the W8 twiddles
+__device__ __forceinline__ void dft8(float2 (&v)[8])
+{
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    const float h = 0.70710678118654752440f;
+    o1 = make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));    // * exp(-i pi/4)
+    o2 = mul_neg_i(o2);                                        // * exp(-i pi/2)
+    o3 = make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));   // * exp(-3i pi/4)
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+// ------------------------------------------------------------------ kernel
+
+struct OfdmParams {
+    int B, S, N, Ncp, W;
+    int xcd_remap;
+    float scale;       // N^-1/2
+    const float2 *x;   // [B][S][Ncp + N]
+    float2 *y;         // [W][S][B]
+};
+
+template <int N>
+struct FftShape {
+    static constexpr int T = N / 8;                    // threads per FFT
+    static constexpr int F = T >= 256 ? 1 : 256 / T;   // FFTs per workgroup
+    static constexpr int LOG = N == 256 ? 8 : N == 512 ? 9 : N == 1024 ? 10 : N == 2048 ? 11 : 12;
+    static constexpr int P8 = LOG / 3;                 // radix-8 passes
+    static constexpr int REM = LOG % 3;                // last pass: 0 none, 1 radix 2, 2 radix 4
+};
+
+// Writes bin m of one FFT to y if it is a used subcarrier.
+__device__ __forceinline__ void put_bin(const OfdmParams &P, int s, int b, int N, int m, float2 X)
+{
+    const int half = P.W >> 1;
+    int w = -1;
+    if (m >= 1 && m <= half) w = m + half - 1;
+    else if (m >= N - half) w = m - (N - half);
+    if (w >= 0)
+        P.y[((size_t)w * P.S + s) * P.B + b] = make_float2(X.x * P.scale, X.y * P.scale);
+}
+
+template <int N>
+__global__ __launch_bounds__(FftShape<N>::T * FftShape<N>::F) void k_ofdm_fft(OfdmParams P)
+{
+    using Sh = FftShape<N>;
+    constexpr int T = Sh::T, F = Sh::F;
+    __shared__ float2 buf[F][N];
+    const int f = threadIdx.x / T, t = threadIdx.x % T;
+    const int tile = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const long g = (long)tile * F + f;                 // FFT index s * B + b
+    const bool live = g < (long)P.S * P.B;
+    const int s = live ? (int)(g / P.B) : 0, b = live ? (int)(g % P.B) : 0;
+    float2 *sh = buf[f];
+
+    // pass 1 (Ns = 1, no twiddles): operands straight from the time-domain symbol
+    const float2 *x = P.x + ((size_t)b * P.S + s) * (P.Ncp + N) + P.Ncp;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = live ? x[t + r * T] : make_float2(0.f, 0.f);
+    dft8(v);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sh[8 * t + q] = v[q];
+    int Ns = 8;
+    __syncthreads();
+
+    // the remaining radix-8 passes through LDS; the last radix-8 pass of a size
+    // that is a power of 8 writes the result directly
+#pragma unroll
+    for (int pass = 1; pass < Sh::P8; ++pass) {
+        const int j = t, k = j & (Ns - 1);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = sh[j + r * T];
+        __syncthreads();   // every operand read before the pass overwrites them
+#pragma unroll
+        for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twiddle<N>(r * k * (N / (Ns * 8))));
+        dft8(v);
+        if (Sh::REM == 0 && pass == Sh::P8 - 1) {
+            // last pass: j < Ns, bin k + q Ns
+            if (live)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) put_bin(P, s, b, N, k + q * Ns, v[q]);
+            return;
+        }
+        const int base = (j / Ns) * Ns * 8 + k;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sh[base + q * Ns] = v[q];
+        Ns *= 8;
+        __syncthreads();
+    }
+
+    if constexpr (Sh::REM == 2) {
+        // radix-4 last pass, Ns = N/4: butterflies j = t, t + T; bins j + q N/4
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = t + h * T;
+            float2 a = sh[j], bb = sh[j + N / 4], c = sh[j + N / 2], d = sh[j + 3 * N / 4];
+            bb = cmul(bb, twiddle<N>(j));
+            c = cmul(c, twiddle<N>(2 * j));
+            d = cmul(d, twiddle<N>(3 * j));
+            dft4(a, bb, c, d);
+            if (live) {
+                put_bin(P, s, b, N, j, a);
+                put_bin(P, s, b, N, j + N / 4, bb);
+                put_bin(P, s, b, N, j + N / 2, c);
+                put_bin(P, s, b, N, j + 3 * N / 4, d);
+            }
+        }
+    } else if constexpr (Sh::REM == 1) {
+        // radix-2 last pass, Ns = N/2: butterflies j = t + h T (h < 4); bins j, j + N/2
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int j = t + h * T;
+            const float2 a = sh[j], c = cmul(sh[j + N / 2], twiddle<N>(j));
+            if (live) {
+                put_bin(P, s, b, N, j, cadd(a, c));
+                put_bin(P, s, b, N, j + N / 2, csub(a, c));
+            }
+        }
+    }
+}
+
+template <int N>
+static hipError_t launch_ofdm_t(const OfdmParams &p, hipStream_t st)
+{
+    using Sh = FftShape<N>;
+    const long nfft = (long)p.B * p.S;
+    const unsigned blocks = (unsigned)((nfft + Sh::F - 1) / Sh::F);
+    hipLaunchKernelGGL((k_ofdm_fft<N>), dim3(blocks), dim3(Sh::T * Sh::F), 0, st, p);
+    return hipGetLastError();
+}
+
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_ofdm_demodulate(const ocd_ofdm_shape *sh, const float *x, float *y,
+                                          hipStream_t stream)
+{
+    using namespace ocd;
+    if (!sh || !x || !y) return OCD_EINVAL;
+    const int N = sh->N;
+    if (N != 256 && N != 512 && N != 1024 && N != 2048 && N != 4096) return OCD_EINVAL;
+    if (sh->B < 1 || sh->S < 1 || sh->Ncp < 0 || sh->Ncp > N) return OCD_EINVAL;
+    if (sh->W < 2 || sh->W % 2 || sh->W / 2 >= N / 2) return OCD_EINVAL;
+    if ((long long)sh->B * sh->S > (1LL << 30)) return OCD_EUNSUPPORTED;
+    OfdmParams P;
+    P.B = sh->B; P.S = sh->S; P.N = N; P.Ncp = sh->Ncp; P.W = sh->W;
+    P.xcd_remap = 1;
+    P.scale = (float)(1.0 / std::sqrt((double)N));
+    P.x = reinterpret_cast<const float2 *>(x);
+    P.y = reinterpret_cast<float2 *>(y);
+    hipError_t e;
+    switch (N) {
+    case 256: e = launch_ofdm_t<256>(P, stream); break;
+    case 512: e = launch_ofdm_t<512>(P, stream); break;
+    case 1024: e = launch_ofdm_t<1024>(P, stream); break;
+    case 2048: e = launch_ofdm_t<2048>(P, stream); break;
+    default: e = launch_ofdm_t<4096>(P, stream); break;
+    }
+    return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}

@@ -230,3 +230,21 @@ def test_fixed_point_detector_checks_its_arguments_on_the_host(lib):
     assert call(dict(mode=2)) == -2      # HYBRID: per-sweep regularisers are not in the design
     assert call(dict(W=0)) == 0
     assert call(dict(W=0, mode=1)) == 0
+
+
+class OfdmShape(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int), ("S", ctypes.c_int), ("N", ctypes.c_int),
+                ("Ncp", ctypes.c_int), ("W", ctypes.c_int)]
+
+
+@pytest.mark.parametrize("bad", [
+    dict(N=1000), dict(N=128), dict(N=8192), dict(Ncp=-1), dict(Ncp=2049), dict(W=1201),
+    dict(W=0), dict(W=2048), dict(W=-2), dict(B=0), dict(S=0)])
+def test_ofdm_shapes_are_checked_on_the_host(lib, bad):
+    lib.ocd_ofdm_demodulate.restype = ctypes.c_int
+    lib.ocd_ofdm_demodulate.argtypes = [ctypes.POINTER(OfdmShape)] + [ctypes.c_void_p] * 3
+    good = dict(B=128, S=14, N=2048, Ncp=144, W=1200)
+    d = ctypes.c_void_p(0x1000)
+    sh = OfdmShape(**{**good, **bad})
+    assert lib.ocd_ofdm_demodulate(ctypes.byref(sh), d, d, None) == -1
+    assert lib.ocd_ofdm_demodulate(ctypes.byref(OfdmShape(**good)), None, d, None) == -1
