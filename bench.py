@@ -292,6 +292,10 @@ def main():
     ap.add_argument("--mmse-only", default=None, metavar="L,VPB",
                     help="only the explicit-MMSE detector on the headline slots with this plan "
                          "(profiled runs); prints its own JSON line")
+    ap.add_argument("--ofdm-only", action="store_true",
+                    help="only the OFDM front end on the headline slots (profiled runs)")
+    ap.add_argument("--fixed-only", action="store_true",
+                    help="only the fixed-point datapath on the headline slots (profiled runs)")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DIR", default=None,
                     help="no GPU work: summarise rocprofv3 CSV output (a --kernel-trace --stats "
                          "directory, or FETCH_SIZE and WRITE_SIZE --pmc directories) and exit")
@@ -337,6 +341,15 @@ def main():
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
     outs = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
              torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
+    if args.ofdm_only or args.fixed_only:
+        pb32 = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
+        if args.ofdm_only:
+            del slots[8:]
+            res = ofdm_form(torch, ocd, synth, dev, args, slots, pb32, float("nan"))
+        else:
+            res = fixed_form(torch, ocd, dev, args, slots, pb32, float("nan"), 0, 0)
+        print(json.dumps(res), flush=True)
+        return
     if args.mmse_only:
         f = [int(x) for x in args.mmse_only.split(",")] + [0]
         mp = ocd.Plan(f[0], f[1], f[2], 0)

@@ -4,22 +4,23 @@
 // -W/2 .. -1 and +1 .. +W/2, DC empty), written straight into the detector's
 // [W][S][B] layout.
 //
-// One FFT per N/8 threads (several FFTs per workgroup for small N), Stockham
+// One FFT per N/8 threads, 8192 / N FFTs per 1024-thread workgroup, Stockham
 // auto-sort passes of radix 8 (then one of radix 4 or 2 when log2 N is not a
 // multiple of 3).  Pass with stride Ns and radix R, butterfly j:
 //   k = j mod Ns,  v_r = in[j + r N/R] * w^(r k), w = exp(-2 pi i / (Ns R)),
 //   out[(j / Ns) Ns R + k + q Ns] = sum_r v_r exp(-2 pi i r q / R).
 // The first pass reads its operands straight from HBM (in[t + r N/8] is the
-// time-domain symbol after the prefix); the last one writes the used bins
-// straight to y; the passes in between exchange through LDS.  Twiddles come from
-// a 4096-entry table of exp(-2 pi i m / 4096), built at compile time in double
-// precision and rounded to FP32.
+// time-domain symbol after the prefix); the passes exchange through LDS.  Each
+// pass loads one twiddle w = exp(-2 pi i k / (Ns R)) per butterfly from a
+// 4096-entry table (built at compile time in double precision, rounded to FP32)
+// and forms w^2 .. w^(R-1) by complex products.
 //
-// Each FFT writes W scattered 8-byte values (consecutive subcarriers are S B
-// entries apart in y); the FFTs of neighbouring antennas of one symbol fill the
-// rest of those cache lines.  Workgroups are mapped so that consecutive FFTs (same
-// symbol, consecutive antennas) run on the same XCD, whose L2 merges the partial
-// lines before they reach HBM.
+// Consecutive subcarriers are S B entries apart in y, so one FFT's outputs are
+// scattered.  A workgroup holds the FFTs of consecutive antennas of one symbol
+// and writes the used bins with the antenna index fastest: contiguous runs of
+// 8 F bytes.  Workgroups are mapped so that consecutive antenna blocks of a
+// symbol run on the same XCD, whose L2 merges the runs into whole lines before
+// they reach HBM.
 #include <cmath>
 
 #include "ocd.h"
@@ -54,8 +55,12 @@ constexpr double ct_cos(double x)
     return sum;
 }
 
+struct TwEntry {
+    float re, im;
+};
+
 struct TwTable {
-    float re[TW_N], im[TW_N];
+    TwEntry e[TW_N];
 };
 
 // exp(-2 pi i m / 4096), the angle taken in (-pi, pi]
@@ -65,8 +70,8 @@ constexpr TwTable make_twiddles()
     for (int m = 0; m < TW_N; ++m) {
         const int mm = m <= TW_N / 2 ? m : m - TW_N;
         const double a = 2.0 * TW_PI * (double)mm / (double)TW_N;
-        t.re[m] = (float)ct_cos(a);
-        t.im[m] = (float)-ct_sin(a);
+        t.e[m].re = (float)ct_cos(a);
+        t.e[m].im = (float)-ct_sin(a);
     }
     return t;
 }
@@ -76,8 +81,8 @@ __device__ const TwTable g_twiddle = make_twiddles();
 template <int N>
 __device__ __forceinline__ float2 twiddle(int m)   // exp(-2 pi i m / N), 0 <= m < N
 {
-    const int i = m * (TW_N / N);
-    return make_float2(g_twiddle.re[i], g_twiddle.im[i]);
+    const TwEntry t = g_twiddle.e[m * (TW_N / N)];   // one 8-byte load
+    return make_float2(t.re, t.im);
 }
 
 // ------------------------------------------------------------------ small DFTs
@@ -89,6 +94,25 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ float2 mul_neg_i(float2 a) { return make_float2(a.y, -a.x); }
+
+// v_r *= w^r for r = 1 .. R-1, from one table value w (each power one complex
+// product away from earlier ones, so the error stays a few FP32 ulps)
+template <int R>
+__device__ __forceinline__ void twiddle_powers(float2 *v, float2 w)
+{
+    float2 p[R];
+    p[1] = w;
+    if constexpr (R > 2) p[2] = cmul(w, w);
+    if constexpr (R > 3) p[3] = cmul(p[2], w);
+    if constexpr (R > 4) {
+        p[4] = cmul(p[2], p[2]);
+        p[5] = cmul(p[4], w);
+        p[6] = cmul(p[3], p[3]);
+        p[7] = cmul(p[6], w);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], p[r]);
+}
 
 // forward DFT of 4 points: X_q = sum_r x_r exp(-2 pi i r q / 4)
 __device__ __forceinline__ void dft4(float2 &a, float2 &b, float2 &c, float2 &d)
@@ -133,36 +157,34 @@ struct OfdmParams {
 
 template <int N>
 struct FftShape {
-    static constexpr int T = N / 8;                    // threads per FFT
-    static constexpr int F = T >= 256 ? 1 : 256 / T;   // FFTs per workgroup
+    static constexpr int T = N / 8;        // threads per FFT
+    static constexpr int F = 8192 / N;     // FFTs per workgroup: 1024 threads, 8192 points
+    static constexpr int LD = N + 8;       // LDS row of one FFT, padded against bank conflicts
     static constexpr int LOG = N == 256 ? 8 : N == 512 ? 9 : N == 1024 ? 10 : N == 2048 ? 11 : 12;
-    static constexpr int P8 = LOG / 3;                 // radix-8 passes
-    static constexpr int REM = LOG % 3;                // last pass: 0 none, 1 radix 2, 2 radix 4
+    static constexpr int P8 = LOG / 3;     // radix-8 passes
+    static constexpr int REM = LOG % 3;    // last pass: 0 none, 1 radix 2, 2 radix 4
 };
 
-// Writes bin m of one FFT to y if it is a used subcarrier.
-__device__ __forceinline__ void put_bin(const OfdmParams &P, int s, int b, int N, int m, float2 X)
+// Bin of used subcarrier w: -W/2 .. -1 first, then +1 .. +W/2.
+__device__ __forceinline__ int used_bin(int N, int W, int w)
 {
-    const int half = P.W >> 1;
-    int w = -1;
-    if (m >= 1 && m <= half) w = m + half - 1;
-    else if (m >= N - half) w = m - (N - half);
-    if (w >= 0)
-        P.y[((size_t)w * P.S + s) * P.B + b] = make_float2(X.x * P.scale, X.y * P.scale);
+    return w < (W >> 1) ? N - (W >> 1) + w : w - (W >> 1) + 1;
 }
 
 template <int N>
-__global__ __launch_bounds__(FftShape<N>::T * FftShape<N>::F) void k_ofdm_fft(OfdmParams P)
+__global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
 {
     using Sh = FftShape<N>;
-    constexpr int T = Sh::T, F = Sh::F;
-    __shared__ float2 buf[F][N];
+    constexpr int T = Sh::T, F = Sh::F, LD = Sh::LD;
+    __shared__ float2 buf[F * LD];
     const int f = threadIdx.x / T, t = threadIdx.x % T;
     const int tile = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const long g = (long)tile * F + f;                 // FFT index s * B + b
-    const bool live = g < (long)P.S * P.B;
+    const long g0 = (long)tile * F;                    // first FFT of the workgroup (s B + b)
+    const long nfft = (long)P.S * P.B;
+    const long g = g0 + f;
+    const bool live = g < nfft;
     const int s = live ? (int)(g / P.B) : 0, b = live ? (int)(g % P.B) : 0;
-    float2 *sh = buf[f];
+    float2 *sh = buf + f * LD;
 
     // pass 1 (Ns = 1, no twiddles): operands straight from the time-domain symbol
     const float2 *x = P.x + ((size_t)b * P.S + s) * (P.Ncp + N) + P.Ncp;
@@ -175,24 +197,15 @@ __global__ __launch_bounds__(FftShape<N>::T * FftShape<N>::F) void k_ofdm_fft(Of
     int Ns = 8;
     __syncthreads();
 
-    // the remaining radix-8 passes through LDS; the last radix-8 pass of a size
-    // that is a power of 8 writes the result directly
+    // the other radix-8 passes, in place in LDS (all operands read before a barrier)
 #pragma unroll
     for (int pass = 1; pass < Sh::P8; ++pass) {
         const int j = t, k = j & (Ns - 1);
 #pragma unroll
         for (int r = 0; r < 8; ++r) v[r] = sh[j + r * T];
-        __syncthreads();   // every operand read before the pass overwrites them
-#pragma unroll
-        for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twiddle<N>(r * k * (N / (Ns * 8))));
+        __syncthreads();
+        twiddle_powers<8>(v, twiddle<N>(k * (N / (Ns * 8))));
         dft8(v);
-        if (Sh::REM == 0 && pass == Sh::P8 - 1) {
-            // last pass: j < Ns, bin k + q Ns
-            if (live)
-#pragma unroll
-                for (int q = 0; q < 8; ++q) put_bin(P, s, b, N, k + q * Ns, v[q]);
-            return;
-        }
         const int base = (j / Ns) * Ns * 8 + k;
 #pragma unroll
         for (int q = 0; q < 8; ++q) sh[base + q * Ns] = v[q];
@@ -201,33 +214,55 @@ __global__ __launch_bounds__(FftShape<N>::T * FftShape<N>::F) void k_ofdm_fft(Of
     }
 
     if constexpr (Sh::REM == 2) {
-        // radix-4 last pass, Ns = N/4: butterflies j = t, t + T; bins j + q N/4
+        // radix-4 last pass, Ns = N/4: butterflies j = t, t + T, in place
+        float2 u[2][4];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int j = t + h * T;
-            float2 a = sh[j], bb = sh[j + N / 4], c = sh[j + N / 2], d = sh[j + 3 * N / 4];
-            bb = cmul(bb, twiddle<N>(j));
-            c = cmul(c, twiddle<N>(2 * j));
-            d = cmul(d, twiddle<N>(3 * j));
-            dft4(a, bb, c, d);
-            if (live) {
-                put_bin(P, s, b, N, j, a);
-                put_bin(P, s, b, N, j + N / 4, bb);
-                put_bin(P, s, b, N, j + N / 2, c);
-                put_bin(P, s, b, N, j + 3 * N / 4, d);
-            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) u[h][r] = sh[j + r * (N / 4)];
         }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = t + h * T;
+            twiddle_powers<4>(u[h], twiddle<N>(j));
+            dft4(u[h][0], u[h][1], u[h][2], u[h][3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sh[j + q * (N / 4)] = u[h][q];
+        }
+        __syncthreads();
     } else if constexpr (Sh::REM == 1) {
-        // radix-2 last pass, Ns = N/2: butterflies j = t + h T (h < 4); bins j, j + N/2
+        // radix-2 last pass, Ns = N/2: butterflies j = t + h T (h < 4), in place
+        float2 u[4][2];
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             const int j = t + h * T;
-            const float2 a = sh[j], c = cmul(sh[j + N / 2], twiddle<N>(j));
-            if (live) {
-                put_bin(P, s, b, N, j, cadd(a, c));
-                put_bin(P, s, b, N, j + N / 2, csub(a, c));
-            }
+            u[h][0] = sh[j];
+            u[h][1] = sh[j + N / 2];
         }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int j = t + h * T;
+            twiddle_powers<2>(u[h], twiddle<N>(j));
+            sh[j] = cadd(u[h][0], u[h][1]);
+            sh[j + N / 2] = csub(u[h][0], u[h][1]);
+        }
+        __syncthreads();
+    }
+    // (a power-of-8 size ends with its last radix-8 pass, already in natural order)
+
+    // write-out: item i = (w, a), a fastest, so F consecutive antennas of one
+    // symbol store one contiguous run of y[w][s][b0 .. b0 + F)
+    const int W = P.W;
+    for (int i = threadIdx.x; i < W * F; i += 1024) {
+        const int w = i / F, a = i - w * F;
+        const long gg = g0 + a;
+        if (gg >= nfft) continue;
+        const int ss = (int)(gg / P.B), bb = (int)(gg % P.B);
+        const float2 X = buf[a * LD + used_bin(N, W, w)];
+        P.y[((size_t)w * P.S + ss) * P.B + bb] = make_float2(X.x * P.scale, X.y * P.scale);
     }
 }
 
@@ -237,7 +272,7 @@ static hipError_t launch_ofdm_t(const OfdmParams &p, hipStream_t st)
     using Sh = FftShape<N>;
     const long nfft = (long)p.B * p.S;
     const unsigned blocks = (unsigned)((nfft + Sh::F - 1) / Sh::F);
-    hipLaunchKernelGGL((k_ofdm_fft<N>), dim3(blocks), dim3(Sh::T * Sh::F), 0, st, p);
+    hipLaunchKernelGGL((k_ofdm_fft<N>), dim3(blocks), dim3(1024), 0, st, p);
     return hipGetLastError();
 }
 
