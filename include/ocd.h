@@ -232,12 +232,15 @@ ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const *H, const 
  *   H, y        device [W][U][B], [W][S][B] complex, as for ocd_detect
  *   z, llr      device outputs [W][S][U] complex FP32 and [W][S][U][Q] FP32, each
  *               may be NULL (not written), not both
- *   plan        lanes_per_vector (8, 16 or 32) and vectors_per_block
- *               (1..512/lanes_per_vector); xcd_remap honoured; channel_in_registers
- *               must be 0.  NULL: a heuristic choice (whole subcarriers per
- *               workgroup where they fit).  OCD_EUNSUPPORTED if the plan's LDS
- *               (H_w of every touched subcarrier plus two U x U work matrices per
- *               subcarrier) exceeds the device's per-workgroup limit.
+ *   plan        lanes_per_vector 8, 16 or 32 with vectors_per_block
+ *               (1..512/lanes_per_vector): lane groups per vector (vector ALUs);
+ *               or lanes_per_vector 0 with vectors_per_block 0 or S: one subcarrier
+ *               per workgroup, the Gram matrix and the S matched filters as real
+ *               matrix products on the FP32 matrix cores (U <= 8, S <= 16).
+ *               xcd_remap honoured; channel_in_registers must be 0.  NULL: lane
+ *               groups with whole subcarriers per workgroup where they fit.  OCD_EUNSUPPORTED if the
+ *               plan does not fit the problem or its LDS exceeds the device's
+ *               per-workgroup limit.
  * Asynchronous on `stream`; no allocation. */
 ocd_status ocd_detect_mmse(const ocd_problem *pb, const void *H, const void *y, float *z,
                            float *llr, const ocd_plan *plan, hipStream_t stream);

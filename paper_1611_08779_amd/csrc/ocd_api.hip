@@ -391,8 +391,35 @@ static bool make_mmse_params(const ocd_problem *pb, const ocd_plan &pl, Params &
     return lds <= (size_t)lds_limit_bytes();
 }
 
+// The matrix-core kernel (plan lanes_per_vector = 0): one subcarrier per
+// workgroup, U <= 8, S <= 16, B rounded up to a multiple of 4 antennas.
+static bool make_mmse_mfma_params(const ocd_problem *pb, const ocd_plan &pl, Params &P,
+                                  size_t &lds)
+{
+    if (pl.lanes_per_vector != 0 || pl.channel_in_registers != 0) return false;
+    if (pb->U > 8 || pb->S > 16) return false;
+    if (pl.vectors_per_block != 0 && pl.vectors_per_block != pb->S) return false;
+    std::memset(&P, 0, sizeof(P));
+    P.B = pb->B; P.U = pb->U; P.W = pb->W; P.S = pb->S; P.K = pb->K; P.Q = pb->Q;
+    P.Bpad = (pb->B + 3) / 4 * 4;
+    P.vpb = pb->S;
+    P.maxslots = 1;
+    P.nblocks = pb->W;
+    P.xcd_remap = pl.xcd_remap ? 1 : 0;
+    P.Es = pb->Es; P.N0 = pb->N0;
+    P.lam_default = pb->N0 / pb->Es;
+    P.sqEs = std::sqrt(pb->Es);
+    P.qscale = qam_scale(pb->Q);
+    P.invU = 1.0f / (float)pb->U;
+    P.invS = 1.0 / (double)pb->S;
+    lds = mmse_mfma_lds_bytes(P.Bpad, pb->U, pb->S);
+    return lds <= (size_t)lds_limit_bytes();
+}
+
 // Whole subcarriers per workgroup where they fit in 256 threads, with at most 8
-// entries of a column per lane; fewer vectors while the LDS does not fit.
+// entries of a column per lane; fewer vectors while the LDS does not fit.  (The
+// matrix-core form is not chosen by default: both forms are bound by the latency
+// of their per-subcarrier chain, and the vector form measured faster.)
 static ocd_plan mmse_heuristic_plan(const ocd_problem *pb)
 {
     int L = 8;
@@ -424,6 +451,16 @@ extern "C" ocd_status ocd_detect_mmse(const ocd_problem *pb, const void *H, cons
     Params P;
     int npl, threads;
     size_t lds;
+    if (pl.lanes_per_vector == 0) {
+        if (!make_mmse_mfma_params(pb, pl, P, lds)) return OCD_EUNSUPPORTED;
+        if (pb->W == 0) return OCD_OK;
+        P.H = H;
+        P.y = y;
+        P.z = reinterpret_cast<float2 *>(z);
+        P.llr = llr;
+        const hipError_t e = launch_mmse_mfma(pb->storage == OCD_STORE_F16, P, lds, stream);
+        return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+    }
     if (!make_mmse_params(pb, pl, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
     if (pb->W == 0) return OCD_OK;
     P.H = H;

@@ -82,6 +82,8 @@ hipError_t launch_forward_reg(int L, int NPL, int UC, bool f16, const Params &p,
                               int threads, hipStream_t s);
 hipError_t launch_mmse(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
                        hipStream_t s);
+hipError_t launch_mmse_mfma(bool f16, const Params &p, size_t lds, hipStream_t s);
+size_t mmse_mfma_lds_bytes(int Kp, int U, int S);
 hipError_t launch_preprocess(bool f16, const Params &p, float *g, float *dinv, float *pp,
                              hipStream_t s);
 hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s);

@@ -45,6 +45,80 @@ __device__ __forceinline__ MmseSmem mmse_carve(unsigned char *smem, const Params
     return s;
 }
 
+// Gauss-Jordan inversion in place by one wave.  Step k maps the work matrix M to M'
+// with
+//   M'_kk = 1/M_kk,  M'_kc = M_kc / M_kk,  M'_ik = -M_ik / M_kk,
+//   M'_ic = M_ic - M_ik M_kc / M_kk  (i, c != k);
+// after U steps M' = A^-1.  A0 holds the two copies of the U x U work matrix (the
+// first one filled with A); each step reads one and writes the other, and the
+// lanes of a wave issue their LDS operations in program order, so step k + 1 sees
+// every write of step k.  Then the gain, SINR and soft-output coefficients of each
+// user from the diagonal of A^-1 (A^-1 G = I - lambda A^-1); gd is the diagonal
+// of G (zero for an all-zero column, whose coefficients are zero).
+__device__ void invert_and_coefficients(const Params &P, float2 *A0, const float *gd, float2 *lc,
+                                        int lane)
+{
+    const int U = P.U, E = U * U;
+    const float lam = P.lam_default;
+    for (int k = 0; k < U; ++k) {
+        const float2 *src = A0 + (k & 1) * E;
+        float2 *dst = A0 + ((k + 1) & 1) * E;
+        const float piv = 1.0f / src[k * U + k].x;   // Hermitian: a real pivot
+        const float2 *rowk = src + k * U;
+        for (int e = lane; e < E; e += 64) {
+            const int i = slot_of_row(P, e), c = e - i * U;   // e / U (e < 2^10)
+            const float2 aik = src[i * U + k], akc = rowk[c], aic = src[e];
+            float2 out;
+            if (i == k) {
+                out = c == k ? make_float2(piv, 0.f) : make_float2(akc.x * piv, akc.y * piv);
+            } else if (c == k) {
+                out = make_float2(-aik.x * piv, -aik.y * piv);
+            } else {
+                const float mx = aik.x * akc.x - aik.y * akc.y;
+                const float my = aik.x * akc.y + aik.y * akc.x;
+                out = make_float2(fmaf(-mx, piv, aic.x), fmaf(-my, piv, aic.y));
+            }
+            dst[e] = out;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    const float2 *Ai = A0 + (U & 1) * E;
+    for (int u = lane; u < U; u += 64) {
+        const float one_minus_mu = lam * Ai[u * U + u].x;
+        const float mu = 1.0f - one_minus_mu, rho = mu / one_minus_mu;
+        float2 co = make_float2(0.f, 0.f);
+        if (gd[u] > 0.f && mu > 0.f && rho > 0.f)
+            co = make_float2(1.0f / (mu * P.sqEs * P.qscale), rho * P.qscale * P.qscale);
+        lc[u] = co;
+    }
+}
+
+// z = A^-1 s for one (user, axis) pair, then its LLRs (item idx = 2u + axis of
+// vector v): Ai the inverse, sv the vector's matched-filter row, co the user's
+// soft-output coefficients.
+__device__ __forceinline__ void solve_and_llr(const Params &P, const float2 *Ai, const float2 *sv,
+                                              float2 co, long v, int idx)
+{
+    const int U = P.U, u = idx >> 1, ax = idx & 1;
+    const float2 *row = Ai + (size_t)u * U;
+    float acc = 0.f;
+    for (int c = 0; c < U; ++c) {
+        const float2 a = row[c], sc = sv[c];
+        // Re: a.x s.x - a.y s.y;  Im: a.x s.y + a.y s.x
+        const float s1 = ax ? sc.y : sc.x, s2 = ax ? sc.x : -sc.y;
+        acc = fmaf(a.x, s1, fmaf(a.y, s2, acc));
+    }
+    if (P.z) reinterpret_cast<float *>(P.z)[v * 2 * U + idx] = acc;
+    if (P.llr) {
+        const int Q = P.Q, half = Q >> 1;
+        float *dst = P.llr + (v * U + u) * Q + ax * half;
+        const float t = acc * co.x;
+        if (half == 3) axis_llrs<3>(t, co.y, dst);
+        else if (half == 2) axis_llrs<2>(t, co.y, dst);
+        else axis_llrs<1>(t, co.y, dst);
+    }
+}
+
 template <int L, int NPL, bool F16>
 __global__ __launch_bounds__(512) void k_mmse(Params P)
 {
@@ -105,48 +179,10 @@ __global__ __launch_bounds__(512) void k_mmse(Params P)
     }
     __syncthreads();
 
-    // 2. Gauss-Jordan inversion in place, one wave per staged subcarrier.  Step k
-    // maps the work matrix M to M' with
-    //   M'_kk = 1/M_kk,  M'_kc = M_kc / M_kk,  M'_ik = -M_ik / M_kk,
-    //   M'_ic = M_ic - M_ik M_kc / M_kk  (i, c != k);
-    // after U steps M' = A^-1.  The lanes of a wave issue their LDS operations in
-    // program order, so step k + 1 sees every write of step k.
+    // 2, 3. inversion and soft-output coefficients, one wave per staged subcarrier
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
-    for (int sl = wave; sl < tile.nslots; sl += nwaves) {
-        float2 *A0 = sm.A + (size_t)sl * 2 * E;
-        for (int k = 0; k < U; ++k) {
-            const float2 *src = A0 + (k & 1) * E;
-            float2 *dst = A0 + ((k + 1) & 1) * E;
-            const float piv = 1.0f / src[k * U + k].x;   // Hermitian: a real pivot
-            const float2 *rowk = src + k * U;
-            for (int e = lane; e < E; e += 64) {
-                const int i = slot_of_row(P, e), c = e - i * U;   // e / U (e < 2^10)
-                const float2 aik = src[i * U + k], akc = rowk[c], aic = src[e];
-                float2 out;
-                if (i == k) {
-                    out = c == k ? make_float2(piv, 0.f) : make_float2(akc.x * piv, akc.y * piv);
-                } else if (c == k) {
-                    out = make_float2(-aik.x * piv, -aik.y * piv);
-                } else {
-                    const float mx = aik.x * akc.x - aik.y * akc.y;
-                    const float my = aik.x * akc.y + aik.y * akc.x;
-                    out = make_float2(fmaf(-mx, piv, aic.x), fmaf(-my, piv, aic.y));
-                }
-                dst[e] = out;
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        // 3. gain, SINR and the soft-output coefficients of each user
-        const float2 *Ai = A0 + (U & 1) * E;
-        for (int u = lane; u < U; u += 64) {
-            const float one_minus_mu = lam * Ai[u * U + u].x;
-            const float mu = 1.0f - one_minus_mu, rho = mu / one_minus_mu;
-            float2 co = make_float2(0.f, 0.f);
-            if (sm.gd[sl * U + u] > 0.f && mu > 0.f && rho > 0.f)
-                co = make_float2(1.0f / (mu * P.sqEs * P.qscale), rho * P.qscale * P.qscale);
-            sm.lc[sl * U + u] = co;
-        }
-    }
+    for (int sl = wave; sl < tile.nslots; sl += nwaves)
+        invert_and_coefficients(P, sm.A + (size_t)sl * 2 * E, sm.gd + sl * U, sm.lc + sl * U, lane);
 
     // 4. matched filter s = H_w^H y (needs only the staged H_w, so the other waves
     // run it while a wave inverts); lane u mod L keeps s_u in the vector's LDS row
@@ -174,27 +210,156 @@ __global__ __launch_bounds__(512) void k_mmse(Params P)
     // z = A^-1 s: lane pair index idx = 2u + axis computes one real component
     const float2 *Ai = sm.A + (size_t)slot * 2 * E + (U & 1) * E;
     const long v = (long)tile.vbase + grp;
-    const int Q = P.Q, half = Q >> 1;
-    for (int idx = j; idx < 2 * U; idx += L) {
-        const int u = idx >> 1, ax = idx & 1;
-        const float2 *row = Ai + (size_t)u * U;
-        float acc = 0.f;
-        for (int c = 0; c < U; ++c) {
-            const float2 a = row[c], s = sv[c];
-            // Re: a.x s.x - a.y s.y;  Im: a.x s.y + a.y s.x
-            const float s1 = ax ? s.y : s.x, s2 = ax ? s.x : -s.y;
-            acc = fmaf(a.x, s1, fmaf(a.y, s2, acc));
+    for (int idx = j; idx < 2 * U; idx += L)
+        solve_and_llr(P, Ai, sv, sm.lc[slot * U + (idx >> 1)], v, idx);
+}
+
+// ------------------------------------------------------------------ matrix cores
+//
+// One subcarrier per 256-thread workgroup (U <= 8 users, S <= 16 symbols).  With
+// X = [Re H, Im H] (B x 16, users past U zero) and Z = [Re Y, Im Y] (B x 32, the S
+// receive vectors, columns past 2S zero), the Gram matrix and the matched filters
+// of all S symbols are the real products X^T X (16 x 16) and X^T Z (16 x 32):
+//   Re G_ij = (X^T X)_{i,j} + (X^T X)_{8+i,8+j},  Im G_ij = (X^T X)_{i,8+j} - (X^T X)_{8+i,j},
+//   Re s_uv = (X^T Z)_{u,v} + (X^T Z)_{8+u,S+v},  Im s_uv = (X^T Z)_{u,S+v} - (X^T Z)_{8+u,v}.
+// Wave 0 forms X^T X and waves 1, 2 the two 16-column tiles of X^T Z on the FP32
+// matrix cores (v_mfma_f32_16x16x4f32: lane l supplies A[l mod 16][l / 16] and
+// B[l / 16][l mod 16] and receives D[4 (l / 16) + r][l mod 16] in register r).  X
+// and Z are staged antenna-major (16 and 32 floats per antenna), so each K step
+// reads one conflict-free float per lane, and for X^T X the A and B operands are
+// the same value.  Then the elimination, z = A^-1 s and the LLRs as above.
+
+typedef float f32x4_mma __attribute__((ext_vector_type(4)));
+
+// Bytes of dynamic LDS of the matrix-core kernel for K = Bpad antennas (a
+// multiple of 4) and the problem's U, S.
+size_t mmse_mfma_lds_bytes(int Kp, int U, int S)
+{
+    return (size_t)Kp * 50 * 4          // X (16 floats) and Z (32 floats) per antenna, padded
+           + 16 * 48 * 4                // X^T X | X^T Z
+           + (size_t)2 * U * U * 8      // work matrices
+           + (size_t)U * 8              // soft-output coefficients
+           + (size_t)S * U * 8          // matched filters
+           + (size_t)U * 4;             // Gram diagonal
+}
+
+template <bool F16>
+__global__ __launch_bounds__(256) void k_mmse_mfma(Params P)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int U = P.U, S = P.S, B = P.B, Kp = P.Bpad, E = U * U;
+    // rows of 17 and 33 floats: consecutive antennas fall in different LDS banks
+    constexpr int XS = 17, ZS = 33;
+    float *X = reinterpret_cast<float *>(smem);          // [Kp][XS]
+    float *Z = X + (size_t)Kp * XS;                       // [Kp][ZS]
+    float *D = Z + (size_t)Kp * ZS;                       // [16][48]
+    float2 *A0 = reinterpret_cast<float2 *>(D + 16 * 48); // [2][U][U]
+    float2 *lc = A0 + 2 * E;                              // [U]
+    float2 *sv = lc + U;                                  // [S][U]
+    float *gd = reinterpret_cast<float *>(sv + (size_t)S * U);
+    const int w = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int tid = threadIdx.x;
+
+    // stage X and Z antenna-major, zero-padded: thread tid takes antenna b = tid
+    // (per block of 256 antennas) of every column and every receive vector; all
+    // of a block's loads are issued (branch-free: an invalid element reads the
+    // first entry and is replaced by zero) before any is stored
+    auto load_c = [&](const void *base, size_t i) -> float2 {
+        if constexpr (F16) return half2_to_float2(static_cast<const uint32_t *>(base)[i]);
+        else return static_cast<const float2 *>(base)[i];
+    };
+    const float2 zero2 = make_float2(0.f, 0.f);
+    for (int b0 = 0; b0 < Kp; b0 += 256) {
+        const int bb = b0 + tid;
+        const bool ok = bb < B;
+        float2 hx[8], hy[16];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool v_ok = ok && u < U;
+            const float2 h = load_c(P.H, v_ok ? ((size_t)w * U + u) * B + bb : 0);
+            hx[u] = v_ok ? h : zero2;
         }
-        if (P.z) reinterpret_cast<float *>(P.z)[v * 2 * U + idx] = acc;
-        if (P.llr) {
-            const float2 co = sm.lc[slot * U + u];
-            float *dst = P.llr + (v * U + u) * Q + ax * half;
-            const float t = acc * co.x;
-            if (half == 3) axis_llrs<3>(t, co.y, dst);
-            else if (half == 2) axis_llrs<2>(t, co.y, dst);
-            else axis_llrs<1>(t, co.y, dst);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const bool v_ok = ok && v < S;
+            const float2 yv = load_c(P.y, v_ok ? ((size_t)w * S + v) * B + bb : 0);
+            hy[v] = v_ok ? yv : zero2;
+        }
+        if (bb < Kp) {
+            float *xr = X + bb * XS, *zr = Z + bb * ZS;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                xr[u] = hx[u].x;
+                xr[8 + u] = hx[u].y;
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                if (v < S) {
+                    zr[v] = hy[v].x;
+                    zr[S + v] = hy[v].y;
+                }
+            }
+            for (int c = 2 * S; c < 32; ++c) zr[c] = 0.f;   // columns 2S .. 31
         }
     }
+    __syncthreads();
+
+    // X^T X (wave 0), X^T Z columns 0-15 (wave 1) and 16-31 (wave 2); two chains
+    const int wave = tid >> 6, lane = tid & 63;
+    if (wave < 3) {
+        const int i = lane & 15, kk = lane >> 4;
+        f32x4_mma c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        const float *zc = Z + (wave > 0 ? (wave - 1) * 16 : 0) + i;
+        for (int kb = 0; kb < Kp; kb += 8) {
+            const float a0 = X[(kb + kk) * XS + i];
+            const float b0 = wave == 0 ? a0 : zc[(kb + kk) * ZS];
+            c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, c0, 0, 0, 0);
+            if (kb + 4 < Kp) {
+                const float a1 = X[(kb + 4 + kk) * XS + i];
+                const float b1 = wave == 0 ? a1 : zc[(kb + 4 + kk) * ZS];
+                c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, c1, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) D[(4 * kk + r) * 48 + wave * 16 + i] = c0[r] + c1[r];
+    }
+    __syncthreads();
+
+    // A = G + lambda I and the matched filters from the real blocks
+    const float lam = P.lam_default;
+    for (int e = tid; e < E; e += 256) {
+        const int i = slot_of_row(P, e), j = e - i * U;
+        const float gr = D[i * 48 + j] + D[(8 + i) * 48 + 8 + j];
+        const float gi = D[i * 48 + 8 + j] - D[(8 + i) * 48 + j];
+        if (i == j) {
+            A0[e] = make_float2(gr + lam, 0.f);
+            gd[i] = gr;
+        } else {
+            A0[e] = make_float2(gr, gi);
+        }
+    }
+    for (int e = tid; e < S * U; e += 256) {
+        const int v = e / U, u = e - v * U;
+        const float mr = D[u * 48 + 16 + v] + D[(8 + u) * 48 + 16 + S + v];
+        const float mi = D[u * 48 + 16 + S + v] - D[(8 + u) * 48 + 16 + v];
+        sv[e] = make_float2(mr, mi);
+    }
+    __syncthreads();
+    if (wave == 0) invert_and_coefficients(P, A0, gd, lc, lane);
+    __syncthreads();
+
+    const float2 *Ai = A0 + (U & 1) * E;
+    for (int e = tid; e < S * 2 * U; e += 256) {
+        const int v = e / (2 * U), idx = e - v * 2 * U;
+        solve_and_llr(P, Ai, sv + (size_t)v * U, lc[idx >> 1], (long)w * S + v, idx);
+    }
+}
+
+hipError_t launch_mmse_mfma(bool f16, const Params &p, size_t lds, hipStream_t s)
+{
+    if (f16) hipLaunchKernelGGL((k_mmse_mfma<true>), dim3(p.nblocks), dim3(256), lds, s, p);
+    else hipLaunchKernelGGL((k_mmse_mfma<false>), dim3(p.nblocks), dim3(256), lds, s, p);
+    return hipGetLastError();
 }
 
 template <int L, int NPL>

@@ -197,6 +197,11 @@ def test_mmse_detector_checks_its_arguments_on_the_host(lib):
     assert call(plan=(4, 16, 0, 0)) == -2               # lane groups of 8, 16 or 32
     assert call(plan=(16, 14, 0, 1)) == -2              # channel in registers: OCD only
     assert call(plan=(16, 33, 0, 0)) == -2              # more than 512 lanes per workgroup
+    assert call(dict(W=0), plan=(0, 14, 0, 0)) == 0     # matrix cores: U <= 8, S <= 16
+    assert call(dict(W=0), plan=(0, 0, 1, 0)) == 0
+    assert call(plan=(0, 7, 0, 0)) == -2                # one subcarrier per workgroup: S
+    assert call(dict(U=9), plan=(0, 14, 0, 0)) == -2
+    assert call(dict(S=17), plan=(0, 17, 0, 0)) == -2
     assert call(dict(W=0), plan=(16, 14, 0, 0)) == 0    # nothing to do
 
 

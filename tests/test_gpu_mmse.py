@@ -63,8 +63,8 @@ def run_mmse(ocd, B, U, W, S, Q, snr, seed, Es=1.0, plan=None, ztol=None, ltol=N
 
 
 # the headline shape on a slice of subcarriers, under several plans
-@pytest.mark.parametrize("plan", [None, (16, 14, 0), (16, 28, 1), (16, 16, 0), (8, 14, 0),
-                                  (32, 14, 0), (16, 5, 0)])
+@pytest.mark.parametrize("plan", [None, (0, 14, 0), (0, 0, 1), (16, 14, 0), (16, 28, 1), (16, 16, 0),
+                                  (8, 14, 0), (32, 14, 0), (16, 5, 0)])
 def test_b128_u8_s14_64qam_plans(ocd, plan):
     run_mmse(ocd, 128, 8, 60, 14, 6, 20.0, [50, 1], plan=plan)
 
@@ -165,3 +165,43 @@ def test_rejects_box_and_bad_plans(ocd):
     with pytest.raises(ocd.OCDError) as ei:
         ocd.detect_mmse(H, y, 4, 0.1, plan=(4, 8))
     assert ei.value.status == -2
+
+
+# the matrix-core form (plan lanes_per_vector = 0): U <= 8, S <= 16
+@pytest.mark.parametrize("B,U,W,S,Q,snr", [
+    (100, 8, 17, 3, 6, 18.0),    # B not a multiple of 8 (K padded to 100), S = 3
+    (33, 4, 11, 2, 2, 8.0),      # odd B (K padded to 36)
+    (16, 1, 9, 5, 4, 6.0),       # one user
+    (64, 6, 10, 16, 4, 12.0),    # S = 16: all 32 columns of the matched-filter product
+    (512, 8, 3, 1, 6, 15.0),     # the largest B, one symbol
+    (24, 7, 5, 9, 6, 20.0),      # U = 7, S = 9
+])
+def test_matrix_core_form(ocd, B, U, W, S, Q, snr):
+    run_mmse(ocd, B, U, W, S, Q, snr, [59, B, U, S], plan=(0, S))
+
+
+def test_matrix_core_form_zero_column_and_fp16(ocd):
+    wl = synth.make_workload(32, 4, 12, 6, 4, 10.0, seed=[60])
+    H = wl["H"].copy()
+    H[:, 1, :] = 0
+    N0 = f32(wl["N0"])
+    z, L = ocd.detect_mmse(dev(H), dev(wl["y"]), 4, N0, plan=(0, 6))
+    torch.cuda.synchronize()
+    zo, Lo, _ = oracle.mmse(H, wl["y"], 4, N0=N0)
+    assert np.all(host(z)[:, :, 1] == 0) and np.all(host(L)[:, :, 1] == 0)
+    assert z_rel_err(host(z), zo) <= Z_TOL_F32
+    H16, y16 = to_f16_pairs(wl["H"]), to_f16_pairs(wl["y"])
+    z, L = ocd.detect_mmse(dev(H16), dev(y16), 4, N0, storage="f16", plan=(0, 6))
+    torch.cuda.synchronize()
+    zo, Lo, _ = oracle.mmse(from_f16_pairs(H16), from_f16_pairs(y16), 4, N0=N0)
+    assert z_rel_err(host(z), zo) <= Z_TOL_F32
+    assert llr_rel_err(host(L), Lo) <= LLR_TOL_F32
+
+
+def test_matrix_core_form_rejects_shapes_it_does_not_cover(ocd):
+    wl = synth.make_workload(64, 9, 4, 4, 4, 10.0, seed=[61])
+    with pytest.raises(ocd.OCDError):
+        ocd.detect_mmse(dev(wl["H"]), dev(wl["y"]), 4, 0.1, plan=(0, 4))     # U = 9
+    wl = synth.make_workload(64, 8, 4, 4, 4, 10.0, seed=[61])
+    with pytest.raises(ocd.OCDError):
+        ocd.detect_mmse(dev(wl["H"]), dev(wl["y"]), 4, 0.1, plan=(0, 2))     # not S
