@@ -561,7 +561,7 @@ def mmse_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, errs_ocd, nbits)
         return best[1]
 
     cands = [(16, 14, 0), (16, 28, 0), (16, 14, 1), (32, 14, 0), (8, 14, 0), (8, 28, 0),
-             (16, 7, 0), (32, 7, 0), (16, 16, 0)]
+             (16, 7, 0), (32, 7, 0), (16, 16, 0), (0, 14, 0), (0, 14, 1)]
     plan = best_plan(pbm, slots[0], outs[0], cands)
     fns = [(lambda i=i: ocd.ocd_detect_mmse(pbm, slots[i]["H"], slots[i]["y"], outs[i][0],
                                             outs[i][1], plan)) for i in range(len(slots))]
@@ -575,9 +575,10 @@ def mmse_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, errs_ocd, nbits)
         "speedup_vs_ocd_k3": t_ocd / t, "bit_errors_mmse": errs, "bit_errors_ocd_k3": errs_ocd,
         "bits": nbits, "tflops": flops * W * S / t / 1e12,
         "hbm_frac": nbytes * W * S / t / 1e9 / HBM_PEAK_GBPS, "plan": plan.as_dict(),
-        "kernel": "ocd::k_mmse<%d, %d, false>" % (plan.lanes_per_vector,
-                                                  max(2, 1 << math.ceil(math.log2(
-                                                      max(2, math.ceil(B / plan.lanes_per_vector)))))),
+        "kernel": ("ocd::k_mmse_mfma<false>" if plan.lanes_per_vector == 0 else
+                   "ocd::k_mmse<%d, %d, false>" % (plan.lanes_per_vector,
+                                                   max(2, 1 << math.ceil(math.log2(
+                                                       max(2, math.ceil(B / plan.lanes_per_vector))))))),
     }
     del outs
     # S = 1: every vector has its own H
