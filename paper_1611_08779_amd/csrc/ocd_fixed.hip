@@ -13,10 +13,14 @@
 // are formed in FP32 from the fixed-point z and p, as in the floating-point path.
 //
 // One lane group of L lanes per vector; lane j holds residual entries
-// b = j + L i.  Integer sums are exact, so the order of the cross-lane sums does
-// not matter and the result is bit-exact.  H is read from global memory at every
-// update: the S symbols of a subcarrier read the same columns, which stay in
-// the caches.
+// b = j + L i.  The updates run in FP64 on integer values: every intermediate of
+// the datapath is an integer below 2^53 (products below 2^32, sums below 2^41,
+// d^-1 times a shifted inner product below 2^51), so every FP64 operation on them
+// is exact, a floor after a power-of-two scale is the arithmetic shift, and
+// clamps are the saturation; MI355X runs FP64 FMAs at the FP32 vector rate.  The
+// sums are exact, so the order of the cross-lane sums does not matter and the
+// result is bit-exact.  H is read from global memory at every update: the S
+// symbols of a subcarrier read the same columns, which stay in the caches.
 #include <stdint.h>
 
 #include <cmath>
@@ -73,6 +77,37 @@ __device__ __forceinline__ long long dpp_get_i64(long long x)
 
 // Exact sum over the L lanes of an aligned group (L = 16 or 32), the same in
 // every lane; integer addition is associative, so the order does not matter.
+// exact FP64 helpers on integer values (see the header)
+__device__ __forceinline__ double fx_sat16d(double v) { return fmin(fmax(v, -32768.0), 32767.0); }
+
+// v / 2^s rounded half up: floor((v + 2^(s-1)) 2^-s), exact for integer v < 2^53
+__device__ __forceinline__ double fx_round_shiftd(double v, double half, double inv)
+{
+    return floor((v + half) * inv);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_get_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the L lanes of an aligned group (L = 16 or 32), the same in every lane;
+// the values are integers below 2^53, so every partial sum is exact.
+template <int L>
+__device__ __forceinline__ double group_sum_f64(double x)
+{
+    x += dpp_get_f64<DPP_QUAD_XOR1>(x);
+    x += dpp_get_f64<DPP_QUAD_XOR2>(x);
+    x += dpp_get_f64<DPP_ROW_HALF_MIRROR>(x);
+    x += dpp_get_f64<DPP_ROW_MIRROR>(x);
+    if constexpr (L >= 32) x += __shfl_xor(x, 16, 32);
+    return x;
+}
+
 template <int L>
 __device__ __forceinline__ long long group_sum_i64(long long x)
 {
@@ -98,12 +133,12 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
     const int16_t *Hw = P.H + (size_t)(v / P.S) * U * B * 2;
     const int16_t *yv = P.y + (size_t)v * B * 2;
 
-    int rr[NPL], ri[NPL];   // residual entries j + L i, Q.11
+    double rr[NPL], ri[NPL];   // residual entries j + L i, Q.11 integers
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
         const int a = j + L * i;
-        rr[i] = a < B ? yv[2 * a] : 0;
-        ri[i] = a < B ? yv[2 * a + 1] : 0;
+        rr[i] = a < B ? (double)yv[2 * a] : 0.0;
+        ri[i] = a < B ? (double)yv[2 * a + 1] : 0.0;
     }
 
     // preprocessing (Alg. 1, initialisation): ||h_u||^2, d_u^-1, p_u
@@ -139,40 +174,46 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
             h[i] = a < B ? hu[a] : 0u;
         }
     };
+    const double inv_b = ldexp(1.0, -b);
     uint32_t hn[NPL];
     load_col(0, hn);
     for (int k = 0; k < P.K; ++k)
         for (int u = 0; u < U; ++u) {
-            int hr[NPL], hi[NPL];
+            double hr[NPL], hi[NPL];
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-                hr[i] = (int)(int16_t)(hn[i] & 0xFFFFu);
-                hi[i] = (int)(int16_t)(hn[i] >> 16);
+                hr[i] = (double)(int16_t)(hn[i] & 0xFFFFu);
+                hi[i] = (double)(int16_t)(hn[i] >> 16);
             }
             // the next update's column is in flight while this one computes
             load_col(u + 1 < U ? u + 1 : 0, hn);
-            long long ire = 0, iim = 0;   // h_u^H r, Q.22
+            double ire = 0.0, iim = 0.0;   // h_u^H r, Q.22 integers
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-                ire += (long long)hr[i] * rr[i] + (long long)hi[i] * ri[i];
-                iim += (long long)hr[i] * ri[i] - (long long)hi[i] * rr[i];
+                ire = fma(hr[i], rr[i], fma(hi[i], ri[i], ire));
+                iim = fma(hr[i], ri[i], fma(-hi[i], rr[i], iim));
             }
-            ire = group_sum_i64<L>(ire) >> b;
-            iim = group_sum_i64<L>(iim) >> b;
-            const long long d = ds[grp][u], p = ps[grp][u];
-            const long long zr = zs[grp][u][0], zi = zs[grp][u][1];
+            ire = floor(group_sum_f64<L>(ire) * inv_b);   // arithmetic shift by b
+            iim = floor(group_sum_f64<L>(iim) * inv_b);
+            const double d = ds[grp][u], p = ps[grp][u];
+            const double zr = zs[grp][u][0], zi = zs[grp][u][1];
             // c = d^-1 h^H r + p z in Q.33, narrowed to Q.11
-            long long cre = fx_sat16(fx_round_shift(d * ire + p * zr * 2048, 22));
-            long long cim = fx_sat16(fx_round_shift(d * iim + p * zi * 2048, 22));
+            const double h22 = 2097152.0, i22 = 1.0 / 4194304.0;
+            double cre = fx_sat16d(fx_round_shiftd(fma(d, ire, p * zr * 2048.0), h22, i22));
+            double cim = fx_sat16d(fx_round_shiftd(fma(d, iim, p * zi * 2048.0), h22, i22));
             if (P.box) {
-                cre = cre > P.beta_fx ? P.beta_fx : (cre < -P.beta_fx ? -P.beta_fx : cre);
-                cim = cim > P.beta_fx ? P.beta_fx : (cim < -P.beta_fx ? -P.beta_fx : cim);
+                const double bt = P.beta_fx;
+                cre = fmin(fmax(cre, -bt), bt);
+                cim = fmin(fmax(cim, -bt), bt);
             }
-            const long long dre = cre - zr, dim = cim - zi;
+            const double dre = cre - zr, dim = cim - zi;
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-                rr[i] = (int)fx_sat16(rr[i] - fx_round_shift(hr[i] * dre - hi[i] * dim, 11));
-                ri[i] = (int)fx_sat16(ri[i] - fx_round_shift(hr[i] * dim + hi[i] * dre, 11));
+                // r - round(h (c - z) / 2^11), each component saturated
+                const double tr = floor(fma(hr[i], dre, fma(-hi[i], dim, 1024.0)) * (1.0 / 2048.0));
+                const double ti = floor(fma(hr[i], dim, fma(hi[i], dre, 1024.0)) * (1.0 / 2048.0));
+                rr[i] = fx_sat16d(rr[i] - tr);
+                ri[i] = fx_sat16d(ri[i] - ti);
             }
             __builtin_amdgcn_wave_barrier();   // every lane has read z_u
             if (j == 0) {
