@@ -64,6 +64,43 @@ __device__ __forceinline__ float group_sum(float x)
     return x;
 }
 
+// group_sum of two values, level by level: each DPP add reads a register written
+// two instructions earlier, so the two chains cover each other's DPP read
+// hazard.  The scheduling barriers keep the levels interleaved (left alone, the
+// scheduler runs one chain after the other and pads each level with wait states).
+template <int L>
+__device__ __forceinline__ float2 group_sum2(float2 v)
+{
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (L >= 2) {
+        v.x += dpp_get<DPP_QUAD_XOR1>(v.x);
+        v.y += dpp_get<DPP_QUAD_XOR1>(v.y);
+    }
+    if constexpr (L >= 4) {
+        v.x += dpp_get<DPP_QUAD_XOR2>(v.x);
+        v.y += dpp_get<DPP_QUAD_XOR2>(v.y);
+    }
+    if constexpr (L >= 8) {
+        v.x += dpp_get<DPP_ROW_HALF_MIRROR>(v.x);
+        v.y += dpp_get<DPP_ROW_HALF_MIRROR>(v.y);
+    }
+    if constexpr (L >= 16) {
+        v.x += dpp_get<DPP_ROW_MIRROR>(v.x);
+        v.y += dpp_get<DPP_ROW_MIRROR>(v.y);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (L >= 32) {
+        v.x += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v.x), 0x401F));
+        v.y += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v.y), 0x401F));
+    }
+    if constexpr (L >= 64) {
+        const int src = (static_cast<int>(__lane_id()) ^ 32) << 2;
+        v.x += __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v.x)));
+        v.y += __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v.y)));
+    }
+    return v;
+}
+
 // Full-wavefront sum (64 lanes), identical in every lane.
 __device__ __forceinline__ float wave_sum(float x) { return group_sum<64>(x); }
 

@@ -159,11 +159,17 @@ template <int N>
 struct FftShape {
     static constexpr int T = N / 8;        // threads per FFT
     static constexpr int F = 8192 / N;     // FFTs per workgroup: 1024 threads, 8192 points
-    static constexpr int LD = N + 8;       // LDS row of one FFT, padded against bank conflicts
+    static constexpr int LD = N + N / 32 + 8;   // LDS row of one FFT (padded, see lds_index)
     static constexpr int LOG = N == 256 ? 8 : N == 512 ? 9 : N == 1024 ? 10 : N == 2048 ? 11 : 12;
     static constexpr int P8 = LOG / 3;     // radix-8 passes
     static constexpr int REM = LOG % 3;    // last pass: 0 none, 1 radix 2, 2 radix 4
 };
+
+// LDS position of element a of an FFT row: one float2 of padding after every 32.
+// The Stockham passes write with strides of 8 and 64 elements; unpadded, those
+// put 8 or 16 lanes of a wave on the same banks, padded at most 2 (the floor for
+// 8-byte accesses).
+__device__ __forceinline__ int lds_index(int a) { return a + (a >> 5); }
 
 // Bin of used subcarrier w: -W/2 .. -1 first, then +1 .. +W/2.
 __device__ __forceinline__ int used_bin(int N, int W, int w)
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
     for (int r = 0; r < 8; ++r) v[r] = live ? x[t + r * T] : make_float2(0.f, 0.f);
     dft8(v);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sh[8 * t + q] = v[q];
+    for (int q = 0; q < 8; ++q) sh[lds_index(8 * t + q)] = v[q];
     int Ns = 8;
     __syncthreads();
 
@@ -202,13 +208,13 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
     for (int pass = 1; pass < Sh::P8; ++pass) {
         const int j = t, k = j & (Ns - 1);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = sh[j + r * T];
+        for (int r = 0; r < 8; ++r) v[r] = sh[lds_index(j + r * T)];
         __syncthreads();
         twiddle_powers<8>(v, twiddle<N>(k * (N / (Ns * 8))));
         dft8(v);
         const int base = (j / Ns) * Ns * 8 + k;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sh[base + q * Ns] = v[q];
+        for (int q = 0; q < 8; ++q) sh[lds_index(base + q * Ns)] = v[q];
         Ns *= 8;
         __syncthreads();
     }
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
         for (int h = 0; h < 2; ++h) {
             const int j = t + h * T;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) u[h][r] = sh[j + r * (N / 4)];
+            for (int r = 0; r < 4; ++r) u[h][r] = sh[lds_index(j + r * (N / 4))];
         }
         __syncthreads();
 #pragma unroll
@@ -229,7 +235,7 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
             twiddle_powers<4>(u[h], twiddle<N>(j));
             dft4(u[h][0], u[h][1], u[h][2], u[h][3]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) sh[j + q * (N / 4)] = u[h][q];
+            for (int q = 0; q < 4; ++q) sh[lds_index(j + q * (N / 4))] = u[h][q];
         }
         __syncthreads();
     } else if constexpr (Sh::REM == 1) {
@@ -238,16 +244,16 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             const int j = t + h * T;
-            u[h][0] = sh[j];
-            u[h][1] = sh[j + N / 2];
+            u[h][0] = sh[lds_index(j)];
+            u[h][1] = sh[lds_index(j + N / 2)];
         }
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             const int j = t + h * T;
             twiddle_powers<2>(u[h], twiddle<N>(j));
-            sh[j] = cadd(u[h][0], u[h][1]);
-            sh[j + N / 2] = csub(u[h][0], u[h][1]);
+            sh[lds_index(j)] = cadd(u[h][0], u[h][1]);
+            sh[lds_index(j + N / 2)] = csub(u[h][0], u[h][1]);
         }
         __syncthreads();
     }
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
         const long gg = g0 + a;
         if (gg >= nfft) continue;
         const int ss = (int)(gg / P.B), bb = (int)(gg % P.B);
-        const float2 X = buf[a * LD + used_bin(N, W, w)];
+        const float2 X = buf[a * LD + lds_index(used_bin(N, W, w))];
         P.y[((size_t)w * P.S + ss) * P.B + bb] = make_float2(X.x * P.scale, X.y * P.scale);
     }
 }

@@ -435,9 +435,7 @@ template <int L, int NPL, bool BOX, int CHAINS = 1, typename HT>
 __device__ __forceinline__ float2 coordinate_update(const HT *h, float2 dp, float2 zo,
                                                     float beta, float2 *r)
 {
-    float2 ip = partial_inner<NPL, CHAINS>(h, r);
-    ip.x = group_sum<L>(ip.x);
-    ip.y = group_sum<L>(ip.y);
+    const float2 ip = group_sum2<L>(partial_inner<NPL, CHAINS>(h, r));
     float cr = fmaf(dp.x, ip.x, dp.y * zo.x);
     float ci = fmaf(dp.x, ip.y, dp.y * zo.y);
     if constexpr (BOX) {
