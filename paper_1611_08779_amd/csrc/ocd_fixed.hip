@@ -25,7 +25,7 @@
 
 #include <cmath>
 
-#include "ocd.h"
+#include "ocd_api_internal.h"
 #include "ocd_stage.h"
 
 namespace ocd {
@@ -272,8 +272,6 @@ static hipError_t launch_fx(const FxParams &p, hipStream_t s)
     if (p.B <= 512) return launch_fx_t<32, 16>(p, s);
     return launch_fx_t<32, 32>(p, s);
 }
-
-ocd_status validate(const ocd_problem *pb);
 
 }  // namespace ocd
 
