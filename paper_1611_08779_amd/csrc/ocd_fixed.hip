@@ -75,9 +75,7 @@ __device__ __forceinline__ long long dpp_get_i64(long long x)
     return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// Exact sum over the L lanes of an aligned group (L = 16 or 32), the same in
-// every lane; integer addition is associative, so the order does not matter.
-// exact FP64 helpers on integer values (see the header)
+// Exact FP64 helpers on integer values (see the header).
 __device__ __forceinline__ double fx_sat16d(double v) { return fmin(fmax(v, -32768.0), 32767.0); }
 
 // v / 2^s rounded half up: floor((v + 2^(s-1)) 2^-s), exact for integer v < 2^53
@@ -108,6 +106,8 @@ __device__ __forceinline__ double group_sum_f64(double x)
     return x;
 }
 
+// Exact sum over the L lanes of an aligned group (L = 16 or 32), the same in
+// every lane; integer addition is associative, so the order does not matter.
 template <int L>
 __device__ __forceinline__ long long group_sum_i64(long long x)
 {
