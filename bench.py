@@ -600,6 +600,27 @@ def mmse_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, errs_ocd, nbits)
     return res
 
 
+def device_copy_rate(torch, dev, nbytes, reps=50):
+    """HBM rate (GB/s, bytes read + written) of torch's device-to-device copy of
+    `nbytes`, cycling over 4 sources so that no source stays in the caches: what a
+    plain streaming kernel attains on this GPU, next to the published peak."""
+    n = nbytes // 4
+    src = [torch.randn(n, device=dev) for _ in range(4)]
+    dst = torch.empty(n, device=dev)
+    for i in range(8):
+        dst.copy_(src[i % 4])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        dst.copy_(src[i % 4])
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * n * 4 / t / 1e9
+
+
 def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     forms = {}
     B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
@@ -650,7 +671,8 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     # ---- S = 1: one channel matrix per vector (HBM-bound shape)
     log("form: S=1 variant")
     W1 = W * S
-    res = {}
+    _, bytes_f32 = algorithmic(B, U, 1, K, Q, cbytes=8)
+    res = {"device_copy_GBps": device_copy_rate(torch, dev, int(bytes_f32 * W1))}
     for storage in ("f32", "f16"):
         pbs = ocd.problem(B, U, W1, 1, Q, K, "mmse", storage, N0)
         ins = []
@@ -670,6 +692,7 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
         res[storage] = {"gbps": W1 * U * Q / t1 / 1e9, "ms_per_step": t1 * 1e3,
                         "eager_launch_us": tk * 1e6,
                         "hbm_frac": bytes1 * W1 / t1 / 1e9 / HBM_PEAK_GBPS,
+                        "frac_of_device_copy": bytes1 * W1 / t1 / 1e9 / res["device_copy_GBps"],
                         "plan": ocd.ocd_get_plan(pbs).as_dict()}
         del ins, outs
     res["fp16_speedup"] = res["f32"]["ms_per_step"] / res["f16"]["ms_per_step"]
