@@ -185,18 +185,20 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
     __shared__ float2 buf[F * LD];
     const int f = threadIdx.x / T, t = threadIdx.x % T;
     const int tile = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const long g0 = (long)tile * F;                    // first FFT of the workgroup (s B + b)
-    const long nfft = (long)P.S * P.B;
-    const long g = g0 + f;
-    const bool live = g < nfft;
-    const int s = live ? (int)(g / P.B) : 0, b = live ? (int)(g % P.B) : 0;
+    // FFT indices s B + b fit an int: the host admits B S <= 2^30
+    const int g0 = tile * F;                           // first FFT of the workgroup
+    const int nfft = P.S * P.B;
+    // FFTs past the end (last workgroup only) transform the last one again and
+    // are never written, so no branch separates the loads
+    const int g = min(g0 + f, nfft - 1);
+    const int s = g / P.B, b = g - s * P.B;
     float2 *sh = buf + f * LD;
 
     // pass 1 (Ns = 1, no twiddles): operands straight from the time-domain symbol
     const float2 *x = P.x + ((size_t)b * P.S + s) * (P.Ncp + N) + P.Ncp;
     float2 v[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = live ? x[t + r * T] : make_float2(0.f, 0.f);
+    for (int r = 0; r < 8; ++r) v[r] = x[t + r * T];
     dft8(v);
 #pragma unroll
     for (int q = 0; q < 8; ++q) sh[lds_index(8 * t + q)] = v[q];
@@ -260,15 +262,20 @@ __global__ __launch_bounds__(1024) void k_ofdm_fft(OfdmParams P)
     // (a power-of-8 size ends with its last radix-8 pass, already in natural order)
 
     // write-out: item i = (w, a), a fastest, so F consecutive antennas of one
-    // symbol store one contiguous run of y[w][s][b0 .. b0 + F)
+    // symbol store one contiguous run of y[w][s][b0 .. b0 + F).  1024 is a
+    // multiple of F, so every item of a thread has the same a = FFT g0 + a: its
+    // (symbol, antenna) and output column are fixed, and only w steps.
     const int W = P.W;
-    for (int i = threadIdx.x; i < W * F; i += 1024) {
-        const int w = i / F, a = i - w * F;
-        const long gg = g0 + a;
-        if (gg >= nfft) continue;
-        const int ss = (int)(gg / P.B), bb = (int)(gg % P.B);
-        const float2 X = buf[a * LD + lds_index(used_bin(N, W, w))];
-        P.y[((size_t)w * P.S + ss) * P.B + bb] = make_float2(X.x * P.scale, X.y * P.scale);
+    const int a = threadIdx.x % F, ga = g0 + a;
+    if (ga < nfft) {
+        const int sa = ga / P.B, ba = ga - sa * P.B;
+        const size_t wstride = (size_t)P.S * P.B;      // between subcarriers in y
+        const float2 *row = buf + a * LD;
+        float2 *yo = P.y + (size_t)sa * P.B + ba;
+        for (int w = threadIdx.x / F; w < W; w += 1024 / F) {
+            const float2 X = row[lds_index(used_bin(N, W, w))];
+            yo[(size_t)w * wstride] = make_float2(X.x * P.scale, X.y * P.scale);
+        }
     }
 }
 
