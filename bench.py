@@ -502,7 +502,7 @@ def ofdm_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, N=2048, Ncp=144)
             "front_end_plus_ocd_us_per_slot": t2 * 1e6,
             "front_end_plus_ocd_gbps": W * S * U * Q / t2 / 1e9,
             "ocd_alone_us_per_slot": t_ocd * 1e6,
-            "kernel": "ocd::k_ofdm_fft<2048>", "shape": "N=2048, CP=144, W=1200, B=128, S=14"}
+            "kernel": "ocd::k_ofdm_fft<2048, 1024>", "shape": "N=2048, CP=144, W=1200, B=128, S=14"}
 
 
 def fixed_form(torch, ocd, dev, args, slots, pb32, t_ocd, errs_ocd, nbits):

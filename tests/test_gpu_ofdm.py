@@ -38,6 +38,10 @@ def rel_err(yg, yo):
     (4096, 288, 2400, 3, 2),    # radix 8 x 4, 512 threads per FFT
     (2048, 0, 2046, 2, 1),      # no cyclic prefix, every bin but DC and Nyquist
     (2048, 2048, 2, 3, 5),      # a prefix as long as the symbol, two subcarriers
+    # batches large enough for the bigger workgroups on a 256-CU GPU
+    (256, 18, 180, 64, 128),    # 1024 threads, 32 FFTs per workgroup
+    (512, 36, 300, 64, 48),     # 512 threads (1024 would leave CUs idle)
+    (4096, 288, 2400, 64, 8),   # 1024 threads, 2 FFTs per workgroup
 ])
 def test_random_signals(ocd, N, Ncp, W, B, S):
     say("ofdm case N=%d Ncp=%d W=%d B=%d S=%d" % (N, Ncp, W, B, S))
