@@ -264,7 +264,10 @@ ocd_status ocd_detect_mmse(const ocd_problem *pb, const void *H, const void *y, 
  * MMSE mode, 1 in BOX mode; rho = g / lambda, BOX g Es / N0), with ocd_detect's
  * layout and sign.
  *   pb          mode OCD_MMSE or OCD_BOX (OCD_HYBRID: OCD_EUNSUPPORTED); storage is
- *               not used; beta <= 0 selects the constellation edge, rounded to Q.11
+ *               not used; alpha must be below 2^35 (it shares the 36-bit adder with
+ *               g_u), else OCD_EINVAL; beta <= 0 selects the constellation edge,
+ *               rounded to Q.11; a beta of 16 or more (beyond the word range) clips
+ *               nothing
  *   H, y        device int16 (re, im) pairs, [W][U][B][2] and [W][S][B][2], Q5.11
  *   z           device int16 pairs [W][S][U][2], Q5.11, or NULL
  *   llr         device FP32 [W][S][U][Q], or NULL (not both NULL)

@@ -751,7 +751,10 @@ int oracle_mmse(int B, int U, int W, int S, int Q, double N0, double Es, const d
  * F3  b = ceil(log2 B).  ||h_u||^2 + alpha and h_u^H r are shifted right by b
  *     (arithmetic shift: floor); the two shifts cancel in d^-1 h^H r.
  * F4  alpha = lambda (N0/Es in MMSE mode, 0 in BOX mode) enters as the Q.22
- *     integer round(lambda 2^22).
+ *     integer round(lambda 2^22), an operand of the 36-bit adder beside
+ *     ||h_u||^2: alpha >= 2^35 is not representable and is rejected.  beta is a
+ *     Q5.11 word; c is narrowed (F6) before the clip, so a beta of 2^15 LSB or
+ *     more clips nothing and is held at 2^15.
  * F5  Reciprocal of an integer x > 0 of bit length n (x / 2^n in [1/2, 1)):
  *     the index is the 11 bits after the leading one; the table holds the 18-bit
  *     normalised reciprocal round(2^18 / (1 + (i + 1/2) / 2048)) (1/x in Q1.17
@@ -827,7 +830,7 @@ static int ocd_fixed_one(int B, int U, int K, int box, int64_t lam_q, int64_t be
         const int16_t *hu = h + (size_t)2 * u * B;
         int64_t g = 0;
         for (int i = 0; i < B; ++i) g += (int64_t)hu[2 * i] * hu[2 * i] + (int64_t)hu[2 * i + 1] * hu[2 * i + 1];
-        ok &= fx_acc_ok(g);
+        ok &= fx_acc_ok(g) && fx_acc_ok(g + lam_q);
         G[u] = g;
         dinv[u] = fx_recip((g + lam_q) >> b);
         p[u] = fx_sat16(fx_round_shift(dinv[u] * (g >> b), 22));
@@ -878,8 +881,11 @@ int oracle_ocd_fixed(int B, int U, int W, int S, int K, int Q, int mode, double 
     if (mode == MODE_HYBRID) return -1;
     if (setup(&P, B, U, W, S, K, Q, mode, N0, Es, NULL, beta)) return -1;
     const double lam = P.lambda[0];
-    const int64_t lam_q = (int64_t)floor(lam * 4194304.0 + 0.5);
-    const int64_t beta_fx = (int64_t)floor(P.beta * 2048.0 + 0.5);
+    const double lam_s = floor(lam * 4194304.0 + 0.5);
+    if (!(lam_s < 34359738368.0)) return -1;                  /* alpha < 2^35 (F4) */
+    const int64_t lam_q = (int64_t)lam_s;
+    const double beta_s = floor(P.beta * 2048.0 + 0.5);
+    const int64_t beta_fx = beta_s < 32768.0 ? (int64_t)beta_s : 32768;   /* F4 */
     cplx pts[64];
     unsigned labels[64];
     qam_points(Q, pts, labels);

@@ -283,18 +283,24 @@ extern "C" ocd_status ocd_detect_fixed(const ocd_problem *pb, const int16_t *H, 
     if (st != OCD_OK) return st;
     if (!H || !y || (!z && !llr)) return OCD_EINVAL;
     if (pb->mode == OCD_HYBRID) return OCD_EUNSUPPORTED;
-    if (pb->W == 0) return OCD_OK;
     FxParams P;
     P.B = pb->B; P.U = pb->U; P.W = pb->W; P.S = pb->S; P.K = pb->K; P.Q = pb->Q;
     P.box = pb->mode == OCD_BOX;
     P.b = 0;
     while ((1 << P.b) < pb->B) ++P.b;
     const double lam = pb->mode == OCD_MMSE ? (double)pb->N0 / (double)pb->Es : 0.0;
-    P.lam_q = (long long)std::floor(lam * 4194304.0 + 0.5);
+    // alpha = round(lambda 2^22) is an operand of the 36-bit adder beside ||h_u||^2
+    const double lam_s = std::floor(lam * 4194304.0 + 0.5);
+    if (!(lam_s < 34359738368.0)) return OCD_EINVAL;
+    P.lam_q = (long long)lam_s;
     const int M = 1 << (pb->Q / 2);
     const double edge = (double)(M - 1) / std::sqrt(2.0 * (double)(M * M - 1) / 3.0);
     const double beta = pb->beta > 0.f ? (double)pb->beta : edge * std::sqrt((double)pb->Es);
-    P.beta_fx = (int)std::floor(beta * 2048.0 + 0.5);
+    // c is narrowed to a 16-bit word before the clip, so a bound of 2^15 LSB or
+    // more clips nothing: 2^15 stands for all of them
+    const double beta_s = std::floor(beta * 2048.0 + 0.5);
+    P.beta_fx = beta_s < 32768.0 ? (int)beta_s : 32768;
+    if (pb->W == 0) return OCD_OK;
     P.lam = (float)lam;
     P.Es = pb->Es; P.N0 = pb->N0;
     P.sqEs = std::sqrt(pb->Es);

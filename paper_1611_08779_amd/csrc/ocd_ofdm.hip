@@ -22,6 +22,7 @@
 // 8 F bytes.  Workgroups are mapped so that consecutive antenna blocks of a
 // symbol run on the same XCD, whose L2 merges the runs into whole lines before
 // they reach HBM.
+#include <atomic>
 #include <cmath>
 
 #include "ocd.h"
@@ -309,16 +310,19 @@ static hipError_t launch_ofdm_t(const OfdmParams &p, int ncu, hipStream_t st)
     return launch_ofdm_nt<N, 512>(p, st);
 }
 
-// Compute units of the current device (cached per device).
+// Compute units of the current device (cached per device; 0 on error).
 static int device_cus()
 {
-    static int cus[64] = {};
+    static std::atomic<int> cus[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
-    if (dev < 64 && cus[dev] > 0) return cus[dev];
+    if (dev < 64) {
+        const int c = cus[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
     int n = 0;
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (dev < 64) cus[dev] = n;
+    if (dev < 64) cus[dev].store(n, std::memory_order_relaxed);
     return n;
 }
 

@@ -235,6 +235,11 @@ def test_fixed_point_detector_checks_its_arguments_on_the_host(lib):
     assert call(dict(mode=2)) == -2      # HYBRID: per-sweep regularisers are not in the design
     assert call(dict(W=0)) == 0
     assert call(dict(W=0, mode=1)) == 0
+    # alpha = round(N0/Es 2^22) must fit the 36-bit adder: checked before any launch
+    assert call(dict(N0=1e7)) == -1
+    assert call(dict(N0=8000.0, W=0)) == 0
+    assert call(dict(N0=1e7, mode=1, W=0)) == 0     # BOX has no regulariser
+    assert call(dict(beta=1e30, mode=1, W=0)) == 0  # a bound beyond the word range is no error
 
 
 class OfdmShape(ctypes.Structure):

@@ -62,6 +62,7 @@ def test_bit_exact(ocd, B, U, W, S, Q, K, mode, snr):
 def test_symbol_energy_and_given_box(ocd):
     Hq, yq, N0, _ = fixed_workload(64, 8, 10, 4, 4, 12.0, [71])
     run_fixed(ocd, Hq, yq, 3, 4, "box", N0, Es=1.0, beta=0.8)
+    run_fixed(ocd, Hq, yq, 3, 4, "box", N0, Es=1.0, beta=1e30)   # beyond the word range: no clip
     wl_scale = np.sqrt(2.0)
     run_fixed(ocd, Hq, np.clip(np.round(yq * wl_scale), -32768, 32767).astype(np.int16), 3, 4,
               "mmse", N0 * 2.0, Es=2.0)

@@ -141,3 +141,30 @@ def test_36_bit_range_is_enforced():
     y = np.full((1, 1, B, 2), 32767, np.int16)
     with pytest.raises(ValueError):
         oracle.ocd_fixed(H, y, 1, 2, "mmse", N0=1.0)
+
+
+def test_regulariser_must_fit_the_adder():
+    """F4: alpha = round(lambda 2^22) is an operand of the 36-bit adder beside
+    ||h_u||^2; a lambda whose alpha reaches 2^35 (lambda >= 8192) is rejected, one
+    well inside it is not."""
+    Hq, yq, N0, _ = fixed_workload(32, 4, 2, 2, 4, 10.0, [64])
+    oracle.ocd_fixed(Hq, yq, 2, 4, "mmse", N0=4000.0)
+    with pytest.raises(ValueError):
+        oracle.ocd_fixed(Hq, yq, 2, 4, "mmse", N0=8192.0)
+    with pytest.raises(ValueError):
+        oracle.ocd_fixed(Hq, yq, 2, 4, "mmse", N0=1e7)
+
+
+def test_box_bound_beyond_the_word_clips_nothing():
+    """F4, F6: c is narrowed to a 16-bit word before the clip, so a box bound of 16
+    or more leaves BOX mode with no regulariser and no clip: bit for bit the MMSE
+    iteration with alpha = 0 (N0 so small that round(N0 2^22) = 0).  At low SNR
+    some components of c exceed the constellation edge, so the edge bound would
+    clip (checked: it changes z)."""
+    Hq, yq, _, _ = fixed_workload(64, 8, 6, 3, 4, 0.0, [65])
+    zb, _ = oracle.ocd_fixed(Hq, yq, 3, 4, "box", N0=0.1, beta=1e30)
+    zb16, _ = oracle.ocd_fixed(Hq, yq, 3, 4, "box", N0=0.1, beta=16.0)
+    zm, _ = oracle.ocd_fixed(Hq, yq, 3, 4, "mmse", N0=1e-9)
+    ze, _ = oracle.ocd_fixed(Hq, yq, 3, 4, "box", N0=0.1)
+    assert np.array_equal(zb, zm) and np.array_equal(zb16, zm)
+    assert not np.array_equal(ze, zm)
