@@ -299,6 +299,12 @@ def main():
                     help="only the OFDM front end on the headline slots (profiled runs)")
     ap.add_argument("--fixed-only", action="store_true",
                     help="only the fixed-point datapath on the headline slots (profiled runs)")
+    ap.add_argument("--s1-only", action="store_true",
+                    help="only the S=1 form (one H per vector); with --plan L,VPB the register "
+                         "plan is fixed instead of autotuned (profiled runs)")
+    ap.add_argument("--fwdbwd-only", action="store_true",
+                    help="only the forward+backward step of the differentiable workload "
+                         "(profiled runs)")
     ap.add_argument("--summarize-profile", nargs="+", metavar="DIR", default=None,
                     help="no GPU work: summarise rocprofv3 CSV output (a --kernel-trace --stats "
                          "directory, or FETCH_SIZE and WRITE_SIZE --pmc directories) and exit")
@@ -337,6 +343,8 @@ def main():
 
     # ---------------------------------------------------------------- headline
     B, U, W, S, Q, K, snr = 128, 8, 1200, 14, 6, 3, 20.0
+    if args.s1_only or args.fwdbwd_only:
+        args.slots = 1          # the headline slot only fixes N0
     log("generating %d slots of B=%d U=%d W=%d S=%d (64-QAM, %g dB)" % (args.slots, B, U, W, S, snr))
     slots = [synth.make_workload_device(B, U, W, S, Q, snr, seed=1000 + i, device=dev)
              for i in range(args.slots)]
@@ -344,6 +352,14 @@ def main():
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
     outs = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
              torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
+    if args.s1_only or args.fwdbwd_only:
+        if args.s1_only:
+            fixed = [int(x) for x in args.plan.split(",")][:2] if args.plan else None
+            res = s1_form(torch, ocd, synth, dev, args, pb, plan=fixed)
+        else:
+            res = fwd_bwd_form(torch, np, ocd, synth, dev)
+        print(json.dumps(res), flush=True)
+        return
     if args.ofdm_only or args.fixed_only:
         pb32 = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
         if args.ofdm_only:
@@ -621,18 +637,133 @@ def device_copy_rate(torch, dev, nbytes, reps=50):
     return 2.0 * n * 4 / t / 1e9
 
 
+def as_f16(torch, t):
+    """complex64 tensor -> FP16 (re, im) pairs, the FP16-storage input format."""
+    return torch.view_as_real(t).to(torch.float16).contiguous()
+
+
+def s1_form(torch, ocd, synth, dev, args, pb32, storages=("f32", "f16"), plan=None):
+    """The headline vectors with one channel matrix each (S = 1, W = 1200 * 14): no H_w
+    to share, so the kernel streams H and y from HBM.  Autotuned plans unless `plan`
+    (then channel columns in registers with that lane split), graph replays over 4
+    distinct slots; the device-copy rate of a buffer of the slot's size is measured
+    beside it."""
+    log("form: S=1 variant")
+    B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
+    N0 = pb32.N0
+    W1 = W * S
+    _, bytes_f32 = algorithmic(B, U, 1, K, Q, cbytes=8)
+    res = {"device_copy_GBps": device_copy_rate(torch, dev, int(bytes_f32 * W1))}
+    for storage in storages:
+        pbs = ocd.problem(B, U, W1, 1, Q, K, "mmse", storage, N0)
+        ins = []
+        for i in range(4):
+            wl = synth.make_workload_device(B, U, W1, 1, Q, 20.0, seed=2000 + i, device=dev)
+            if storage == "f16":
+                wl = {"H": as_f16(torch, wl["H"]), "y": as_f16(torch, wl["y"])}
+            ins.append(wl)
+        outs = [(torch.empty(W1, 1, U, dtype=torch.complex64, device=dev),
+                 torch.empty(W1, 1, U, Q, dtype=torch.float32, device=dev)) for _ in ins]
+        if plan is None:
+            ocd.ocd_autotune(pbs, ins[0]["H"], ins[0]["y"], outs[0][0], outs[0][1], repeats=3)
+        else:
+            ocd.ocd_set_plan(pbs, ocd.Plan(plan[0], plan[1], 0, 1))
+        fns = [(lambda i=i: ocd.ocd_detect(pbs, ins[i]["H"], ins[i]["y"], z=outs[i][0], llr=outs[i][1]))
+               for i in range(len(ins))]
+        tk = kernel_durations(torch, fns)
+        t1, _ = time_graph(torch, GraphedSteps(torch, fns), max(200, args.steps // 4), 20)
+        _, bytes1 = algorithmic(B, U, 1, K, Q, cbytes=4 if storage == "f16" else 8)
+        res[storage] = {"gbps": W1 * U * Q / t1 / 1e9, "ms_per_step": t1 * 1e3,
+                        "eager_launch_us": tk * 1e6,
+                        "hbm_frac": bytes1 * W1 / t1 / 1e9 / HBM_PEAK_GBPS,
+                        "frac_of_device_copy": bytes1 * W1 / t1 / 1e9 / res["device_copy_GBps"],
+                        "bytes_per_launch": bytes1 * W1,
+                        "plan": ocd.ocd_get_plan(pbs).as_dict()}
+        del ins, outs
+    if "f32" in res and "f16" in res:
+        res["fp16_speedup"] = res["f32"]["ms_per_step"] / res["f16"]["ms_per_step"]
+    return res
+
+
+def fwd_bwd_form(torch, np, ocd, synth, dev):
+    """Forward + backward step of the differentiable workload (B=128, U=16, 2048 x 4,
+    16-QAM, K=4, HYBRID with learnable lambda_k and beta, BCE of the LLRs), tuned
+    forward and backward plans, graph replays."""
+    log("form: forward+backward")
+    B5, U5, W5, S5, Q5, K5 = 128, 16, 2048, 4, 4, 4
+    wl = synth.make_workload_device(B5, U5, W5, S5, Q5, 10.0, seed=4000, device=dev)
+    N05 = float(np.float32(wl["N0"]))
+    lam = torch.full((K5,), N05, device=dev)
+    beta5 = float(3 / math.sqrt(10))
+    pb5 = ocd.problem(B5, U5, W5, S5, Q5, K5, "hybrid", "f32", N05, 1.0, beta5)
+    L5 = torch.empty(W5, S5, U5, Q5, device=dev)
+    zh = torch.empty(W5, S5, K5, U5, dtype=torch.complex64, device=dev)
+    dlam = torch.empty(K5, device=dev)
+    dbeta = torch.empty(1, device=dev)
+    dy = torch.empty(W5, S5, B5, dtype=torch.complex64, device=dev)
+    wsb = torch.empty(ocd.ocd_backward_workspace_bytes(pb5), dtype=torch.uint8, device=dev)
+    bits = wl["bits"].float()
+    inv_n = 1.0 / bits.numel()
+    nbits_s = bits * -inv_n          # -bit / N, fixed labels
+    z5 = torch.empty(W5, S5, U5, dtype=torch.complex64, device=dev)
+    plan_f = ocd.ocd_autotune(pb5, wl["H"], wl["y"], z5, L5, repeats=3)
+    del z5
+
+    def fwd_bwd():
+        ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
+        # gradient of the mean BCE with logits: (sigmoid(L) - bit) / N, two elementwise ops
+        dllr = torch.add(nbits_s, torch.sigmoid(L5), alpha=inv_n)
+        ocd.ocd_detect_backward(pb5, wl["H"], wl["y"], lam, zh, dllr, dlam, dbeta, dy, wsb)
+
+    bits_u8 = wl["bits"].to(torch.uint8).contiguous()
+
+    def fwd_bwd_fused():
+        # the loss gradient formed inside the adjoint kernel from the bits
+        ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
+        ocd.ocd_detect_backward_bce(pb5, wl["H"], wl["y"], lam, zh, bits_u8, dlam, dbeta, dy, wsb)
+
+    def fwd_only():
+        ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
+
+    fwd_only_once = lambda: ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
+    fwd_only_once()
+    dllr0 = (torch.sigmoid(L5) - bits) * inv_n
+    plan_b = ocd.ocd_autotune_backward(pb5, wl["H"], wl["y"], lam, zh, dllr0, dlam, dbeta, dy, wsb,
+                                       repeats=3)
+    del dllr0
+    # the two ways of forming dLoss/dLLR agree (same forward, same bits)
+    fwd_bwd()
+    ref = [t.clone() for t in (dlam, dbeta, dy)]
+    fwd_bwd_fused()
+    torch.cuda.synchronize()
+    agree = all(float((a - b).abs().max()) <= 1e-4 * max(float(b.abs().max()), 1e-30)
+                for a, b in zip((dlam, dbeta, dy), ref))
+    tfb, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd_fused] * 8), 400, 16)
+    tfb2, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd] * 8), 400, 16)
+    tf, _ = time_graph(torch, GraphedSteps(torch, [fwd_only] * 8), 400, 16)
+    fl, _ = algorithmic(B5, U5, S5, K5, Q5)
+    return {
+        "vectors_per_s": W5 * S5 / tfb, "ms_per_step": tfb * 1e3,
+        "loss_gradient": "formed in the adjoint kernel from the bits (ocd_detect_backward_bce)",
+        "two_step_vectors_per_s": W5 * S5 / tfb2,
+        "fused_matches_two_step": bool(agree),
+        "fwd_vectors_per_s": W5 * S5 / tf, "bwd_over_fwd_time": (tfb - tf) / tf,
+        "workload": "B=128 U=16, 2048 subcarriers x 4 symbols, 16-QAM, K=4, HYBRID (learnable "
+                    "lambda_k, beta), BCE of LLRs, 10 dB",
+        "fwd_tflops": fl * W5 * S5 / tf / 1e12,
+        "plan_forward": plan_f.as_dict(), "plan_backward": plan_b.as_dict(),
+    }
+
+
 def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     forms = {}
     B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
     N0 = pb32.N0
 
-    def as_f16(t):
-        return torch.view_as_real(t).to(torch.float16).contiguous()
-
     # ---- FP16 storage of H and y, same slots
     log("form: FP16 storage")
     pb16 = ocd.problem(B, U, W, S, Q, K, "mmse", "f16", N0)
-    s16 = [{"H": as_f16(s["H"]), "y": as_f16(s["y"])} for s in slots]
+    s16 = [{"H": as_f16(torch, s["H"]), "y": as_f16(torch, s["y"])} for s in slots]
     o16 = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
             torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
     ocd.ocd_autotune(pb16, s16[0]["H"], s16[0]["y"], o16[0][0], o16[0][1], repeats=5)
@@ -669,34 +800,7 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     forms["exact_mmse"] = mmse_form(torch, ocd, synth, dev, args, slots, pb32, t32, e32, nb)
 
     # ---- S = 1: one channel matrix per vector (HBM-bound shape)
-    log("form: S=1 variant")
-    W1 = W * S
-    _, bytes_f32 = algorithmic(B, U, 1, K, Q, cbytes=8)
-    res = {"device_copy_GBps": device_copy_rate(torch, dev, int(bytes_f32 * W1))}
-    for storage in ("f32", "f16"):
-        pbs = ocd.problem(B, U, W1, 1, Q, K, "mmse", storage, N0)
-        ins = []
-        for i in range(4):
-            wl = synth.make_workload_device(B, U, W1, 1, Q, 20.0, seed=2000 + i, device=dev)
-            if storage == "f16":
-                wl = {"H": as_f16(wl["H"]), "y": as_f16(wl["y"])}
-            ins.append(wl)
-        outs = [(torch.empty(W1, 1, U, dtype=torch.complex64, device=dev),
-                 torch.empty(W1, 1, U, Q, dtype=torch.float32, device=dev)) for _ in ins]
-        ocd.ocd_autotune(pbs, ins[0]["H"], ins[0]["y"], outs[0][0], outs[0][1], repeats=3)
-        fns = [(lambda i=i: ocd.ocd_detect(pbs, ins[i]["H"], ins[i]["y"], z=outs[i][0], llr=outs[i][1]))
-               for i in range(len(ins))]
-        tk = kernel_durations(torch, fns)
-        t1, _ = time_graph(torch, GraphedSteps(torch, fns), max(200, args.steps // 4), 20)
-        _, bytes1 = algorithmic(B, U, 1, K, Q, cbytes=4 if storage == "f16" else 8)
-        res[storage] = {"gbps": W1 * U * Q / t1 / 1e9, "ms_per_step": t1 * 1e3,
-                        "eager_launch_us": tk * 1e6,
-                        "hbm_frac": bytes1 * W1 / t1 / 1e9 / HBM_PEAK_GBPS,
-                        "frac_of_device_copy": bytes1 * W1 / t1 / 1e9 / res["device_copy_GBps"],
-                        "plan": ocd.ocd_get_plan(pbs).as_dict()}
-        del ins, outs
-    res["fp16_speedup"] = res["f32"]["ms_per_step"] / res["f16"]["ms_per_step"]
-    forms["s1_one_H_per_vector"] = res
+    forms["s1_one_H_per_vector"] = s1_form(torch, ocd, synth, dev, args, pb32)
 
     # ---- 48 uneven jobs: one persistent graph launch vs one launch per job
     log("form: 48 batched jobs")
@@ -766,52 +870,7 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     del Hs, ys, z, L, zs, Ls, ws, gs, call
 
     # ---- differentiable form: forward + backward step (B=128, U=16, 2048 x 4, 16-QAM, K=4)
-    log("form: forward+backward")
-    B5, U5, W5, S5, Q5, K5 = 128, 16, 2048, 4, 4, 4
-    wl = synth.make_workload_device(B5, U5, W5, S5, Q5, 10.0, seed=4000, device=dev)
-    N05 = float(np.float32(wl["N0"]))
-    lam = torch.full((K5,), N05, device=dev)
-    beta5 = float(3 / math.sqrt(10))
-    pb5 = ocd.problem(B5, U5, W5, S5, Q5, K5, "hybrid", "f32", N05, 1.0, beta5)
-    L5 = torch.empty(W5, S5, U5, Q5, device=dev)
-    zh = torch.empty(W5, S5, K5, U5, dtype=torch.complex64, device=dev)
-    dlam = torch.empty(K5, device=dev)
-    dbeta = torch.empty(1, device=dev)
-    dy = torch.empty(W5, S5, B5, dtype=torch.complex64, device=dev)
-    wsb = torch.empty(ocd.ocd_backward_workspace_bytes(pb5), dtype=torch.uint8, device=dev)
-    bits = wl["bits"].float()
-    inv_n = 1.0 / bits.numel()
-    nbits_s = bits * -inv_n          # -bit / N, fixed labels
-    z5 = torch.empty(W5, S5, U5, dtype=torch.complex64, device=dev)
-    plan_f = ocd.ocd_autotune(pb5, wl["H"], wl["y"], z5, L5, repeats=3)
-    del z5
-
-    def fwd_bwd():
-        ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
-        # gradient of the mean BCE with logits: (sigmoid(L) - bit) / N, two elementwise ops
-        dllr = torch.add(nbits_s, torch.sigmoid(L5), alpha=inv_n)
-        ocd.ocd_detect_backward(pb5, wl["H"], wl["y"], lam, zh, dllr, dlam, dbeta, dy, wsb)
-
-    def fwd_only():
-        ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
-
-    fwd_only_once = lambda: ocd.ocd_detect(pb5, wl["H"], wl["y"], lam, z=None, llr=L5, z_hist=zh)
-    fwd_only_once()
-    dllr0 = (torch.sigmoid(L5) - bits) * inv_n
-    plan_b = ocd.ocd_autotune_backward(pb5, wl["H"], wl["y"], lam, zh, dllr0, dlam, dbeta, dy, wsb,
-                                       repeats=3)
-    del dllr0
-    tfb, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd] * 8), 400, 16)
-    tf, _ = time_graph(torch, GraphedSteps(torch, [fwd_only] * 8), 400, 16)
-    fl, _ = algorithmic(B5, U5, S5, K5, Q5)
-    forms["fwd_bwd_differentiable"] = {
-        "vectors_per_s": W5 * S5 / tfb, "ms_per_step": tfb * 1e3,
-        "fwd_vectors_per_s": W5 * S5 / tf, "bwd_over_fwd_time": (tfb - tf) / tf,
-        "workload": "B=128 U=16, 2048 subcarriers x 4 symbols, 16-QAM, K=4, HYBRID (learnable "
-                    "lambda_k, beta), BCE of LLRs, 10 dB",
-        "fwd_tflops": fl * W5 * S5 / tf / 1e12,
-        "plan_forward": plan_f.as_dict(), "plan_backward": plan_b.as_dict(),
-    }
+    forms["fwd_bwd_differentiable"] = fwd_bwd_form(torch, np, ocd, synth, dev)
     return forms
 
 

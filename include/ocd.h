@@ -140,6 +140,22 @@ ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, const void 
                                float *dlambda, float *dbeta, float *dy,
                                void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ocd_detect_backward for the mean binary cross-entropy of the LLRs against the
+ * transmitted bits, with dLoss/dLLR formed inside the adjoint kernel:
+ *   loss = mean over the W S U Q bits of softplus(L) - bit L   (P(bit = 1) = sigmoid(L)),
+ *   dLoss/dL = (sigmoid(L) - bit) / (W S U Q),
+ * L being the max-log LLR of Section III-C of the last sweep's z (z_hist), recomputed (the
+ * value ocd_detect writes, up to rounding).  This is the training step's usual loss
+ * at one launch fewer and with no dLoss/dLLR array.
+ *   bits        device uint8 [W][S][U][Q], 0 or 1, in the LLR layout (MSB of the
+ *               I-axis label first, then the Q-axis label)
+ * Every other argument, the outputs, the workspace and the conventions are those of
+ * ocd_detect_backward; the plan is the one ocd_autotune_backward caches. */
+ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void *H, const void *y,
+                                   const float *lambda, const float *z_hist, const uint8_t *bits,
+                                   float *dlambda, float *dbeta, float *dy,
+                                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* A launch plan: how vectors map onto lanes and workgroups.
  *   lanes_per_vector      lanes that share one (subcarrier, symbol) vector: 4, 8, 16 or 32
  *                         (16 or 32 with channel_in_registers)

@@ -30,7 +30,8 @@ import torch
 __all__ = [
     "Problem", "Plan", "OCDError", "MODES", "STORAGES", "LIB_PATH",
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
-    "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_get_plan", "ocd_set_plan",
+    "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_detect_backward_bce",
+    "ocd_get_plan", "ocd_set_plan",
     "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
     "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed", "ocd_ofdm_demodulate",
     "OfdmShape", "ofdm_demodulate",
@@ -106,6 +107,7 @@ def _load():
         "ocd_detect": ([P, vp, vp, fp, fp, fp, fp, fp, fp, fp, vp], ctypes.c_int),
         "ocd_backward_workspace_bytes": ([P], sz),
         "ocd_detect_backward": ([P, vp, vp, fp, fp, fp, fp, fp, fp, vp, sz, vp], ctypes.c_int),
+        "ocd_detect_backward_bce": ([P, vp, vp, fp, fp, vp, fp, fp, fp, vp, sz, vp], ctypes.c_int),
         "ocd_get_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_set_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_autotune": ([P, vp, vp, fp, fp, ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
@@ -240,6 +242,27 @@ def ocd_detect_backward(pb: Problem, H, y, lam, z_hist, dllr, dlam, dbeta, dy, w
         _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
         _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, _stream(stream))
     _check("ocd_detect_backward", st)
+
+
+def ocd_detect_backward_bce(pb: Problem, H, y, lam, z_hist, bits, dlam, dbeta, dy, workspace,
+                            stream=None) -> None:
+    """ocd_detect_backward for the mean BCE of the LLRs: bits (uint8 [W,S,U,Q]) in
+    place of dLoss/dLLR, which the adjoint kernel forms itself."""
+    dev = H.device
+    f32 = (torch.float32,)
+    zt = (torch.complex64, torch.float32)
+    ws_need = ocd_backward_workspace_bytes(pb)
+    st = _lib.ocd_detect_backward_bce(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(z_hist, "z_hist", zt, pb.W * pb.S * pb.K * pb.U * 8, dev),
+        _dev_ptr(bits, "bits", (torch.uint8,), pb.W * pb.S * pb.U * pb.Q, dev),
+        _dev_ptr(dlam, "dlam", f32, pb.K * 4, dev),
+        _dev_ptr(dbeta, "dbeta", f32, 4, dev),
+        _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
+        _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, _stream(stream))
+    _check("ocd_detect_backward_bce", st)
 
 
 def ocd_get_plan(pb: Problem) -> Plan:
@@ -416,8 +439,10 @@ def detect(H, y, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, lam=None, storage=
 
 
 def backward(H, y, z_hist, dllr, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, lam=None,
-             storage="f32", want_dy=True, stream=None):
-    """Runs ocd_detect_backward; returns (dlam [K], dbeta [1], dy [W,S,B] or None)."""
+             storage="f32", want_dy=True, stream=None, bits=None):
+    """Runs ocd_detect_backward (or, with dllr None and bits given, the fused
+    cross-entropy form ocd_detect_backward_bce); returns (dlam [K], dbeta [1],
+    dy [W,S,B] or None)."""
     W, U, B, S = _shape_of(H, y, storage)
     pb = problem(B, U, W, S, Q, K, mode, storage, N0, Es, beta)
     dev = H.device
@@ -425,7 +450,10 @@ def backward(H, y, z_hist, dllr, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, la
     dbeta = torch.empty(1, device=dev, dtype=torch.float32)
     dy = torch.empty(W, S, B, device=dev, dtype=torch.complex64) if want_dy else None
     ws = torch.empty(ocd_backward_workspace_bytes(pb), device=dev, dtype=torch.uint8)
-    ocd_detect_backward(pb, H, y, lam, z_hist, dllr, dlam, dbeta, dy, ws, stream)
+    if dllr is None:
+        ocd_detect_backward_bce(pb, H, y, lam, z_hist, bits, dlam, dbeta, dy, ws, stream)
+    else:
+        ocd_detect_backward(pb, H, y, lam, z_hist, dllr, dlam, dbeta, dy, ws, stream)
     return dlam, dbeta, dy
 
 

@@ -576,23 +576,28 @@ extern "C" size_t ocd_backward_workspace_bytes(const ocd_problem *pb)
 
 namespace ocd {
 
+// dllr_or_bits: the dLoss/dLLR array or the bits of the fused cross-entropy
 static ocd_status check_backward_args(const ocd_problem *pb, const void *H, const void *y,
-                                      const float *z_hist, const float *dllr, float *dlambda,
-                                      float *dbeta, void *workspace, size_t workspace_bytes)
+                                      const float *z_hist, const void *dllr_or_bits,
+                                      float *dlambda, float *dbeta, void *workspace,
+                                      size_t workspace_bytes)
 {
     ocd_status st = validate(pb);
     if (st != OCD_OK) return st;
     if (!dlambda || !dbeta) return OCD_EINVAL;
-    if (pb->W > 0 && (!H || !y || !z_hist || !dllr)) return OCD_EINVAL;
+    if (pb->W > 0 && (!H || !y || !z_hist || !dllr_or_bits)) return OCD_EINVAL;
     if (workspace_bytes < ocd_backward_workspace_bytes(pb) || !workspace) return OCD_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace) % 16) return OCD_EINVAL;
     return OCD_OK;
 }
 
+// dLoss/dLLR from dllr, or (dllr null) formed in the kernel from bits for the mean
+// binary cross-entropy of the LLRs
 static ocd_status run_backward(const ocd_problem *pb, const ocd_plan &pl, const void *H,
                                const void *y, const float *lambda, const float *z_hist,
                                const float *dllr, float *dlambda, float *dbeta, float *dy,
-                               void *workspace, hipStream_t stream)
+                               void *workspace, hipStream_t stream,
+                               const unsigned char *bits = nullptr)
 {
     Params P;
     int npl, threads;
@@ -601,6 +606,8 @@ static ocd_status run_backward(const ocd_problem *pb, const ocd_plan &pl, const 
     P.H = H; P.y = y;
     P.zh_in = reinterpret_cast<const float2 *>(z_hist);
     P.dllr = dllr;
+    P.bits = dllr ? nullptr : bits;
+    P.inv_nbits = (float)(1.0 / ((double)pb->W * pb->S * pb->U * pb->Q));
     P.dy = reinterpret_cast<float2 *>(dy);
     P.partials = reinterpret_cast<float *>(workspace);
     set_vec_ok(P, pb, H, y);
@@ -628,6 +635,19 @@ extern "C" ocd_status ocd_detect_backward(const ocd_problem *pb, const void *H, 
     if (st != OCD_OK) return st;
     return run_backward(pb, choose_plan(pb, lambda, true), H, y, lambda, z_hist, dllr, dlambda,
                         dbeta, dy, workspace, stream);
+}
+
+extern "C" ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void *H, const void *y,
+                                              const float *lambda, const float *z_hist,
+                                              const uint8_t *bits, float *dlambda, float *dbeta,
+                                              float *dy, void *workspace, size_t workspace_bytes,
+                                              hipStream_t stream)
+{
+    ocd_status st = check_backward_args(pb, H, y, z_hist, bits, dlambda, dbeta, workspace,
+                                        workspace_bytes);
+    if (st != OCD_OK) return st;
+    return run_backward(pb, choose_plan(pb, lambda, true), H, y, lambda, z_hist, nullptr, dlambda,
+                        dbeta, dy, workspace, stream, bits);
 }
 
 extern "C" ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const void *y,

@@ -10,7 +10,8 @@
 //   lambda_bar_k += -d^-1 Re(conj(z_new) c_bar)
 //   z_bar = -Delta_bar + p c_bar,  r_bar += h d^-1 c_bar
 // walked backwards over k = K..1, u = U..1, after seeding z_bar from dLoss/dLLR
-// through the max-log LLR (and lambda_bar_K through mu and rho).  y_bar is r_bar
+// through the max-log LLR (and lambda_bar_K through mu and rho).  dLoss/dLLR is
+// given, or formed here from the transmitted bits for the mean BCE of the LLRs.  y_bar is r_bar
 // at the end; y itself is not read.  Each update costs one lane-local inner
 // product, one 2-float all-reduce and one axpy: the work of a forward update.
 // A component of z_new equal to +-beta counts as clipped (c exactly at +-beta,
@@ -21,10 +22,20 @@
 
 namespace ocd {
 
+// dLoss/dLLR of the mean binary cross-entropy softplus(L) - bit L over n bits
+// (P(bit = 1) = sigmoid(L)): (sigmoid(L) - bit) / n.
+__device__ __forceinline__ float bce_grad(float L, unsigned char bit, float inv_n)
+{
+    return (1.0f / (1.0f + expf(-L)) - (float)bit) * inv_n;
+}
+
 // dLoss/dz of one user from dLoss/dLLR through L_b = rho * D_b(x), x = z/(mu sqrt(Es)),
-// and the contribution of mu(lambda_K), rho(lambda_K) to dLoss/dlambda_K.
+// and the contribution of mu(lambda_K), rho(lambda_K) to dLoss/dlambda_K.  dLoss/dLLR
+// is read from Lbar, or (Lbar null) formed from the user's bits for the mean BCE of
+// the LLRs, L_b recomputed here.
 template <int HALF>
-__device__ __forceinline__ void user_llr_adjoint(const float *Lbar, float xr, float xi, float s,
+__device__ __forceinline__ void user_llr_adjoint(const float *Lbar, const unsigned char *bits,
+                                                 float inv_n, float xr, float xi, float s,
                                                  float mu, float rho, float scale, float2 *zbar,
                                                  float *dmu, float *drho)
 {
@@ -36,7 +47,8 @@ __device__ __forceinline__ void user_llr_adjoint(const float *Lbar, float xr, fl
     for (int bb = 0; bb < HALF; ++bb) {
         const float sr = axis_llr_slope<HALF>(xr, scale, bb);
         const float si = axis_llr_slope<HALF>(xi, scale, bb);
-        const float lr = Lbar[bb], li = Lbar[HALF + bb];
+        const float lr = Lbar ? Lbar[bb] : bce_grad(rho * Dr[bb], bits[bb], inv_n);
+        const float li = Lbar ? Lbar[HALF + bb] : bce_grad(rho * Di[bb], bits[HALF + bb], inv_n);
         xbr = fmaf(lr * rho, sr, xbr);
         xbi = fmaf(li * rho, si, xbi);
         gr = fmaf(lr, Dr[bb], fmaf(li, Di[bb], gr));
@@ -96,11 +108,14 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
         if (active && rho > 0.f && mu > 0.f) {
             const float s = 1.0f / (mu * sqEs);
             const float2 zu = zv[u];
-            const float *Lbar = P.dllr + ((long)v * U + u) * P.Q;
+            const long o = ((long)v * U + u) * P.Q;
+            const float *Lbar = P.dllr ? P.dllr + o : nullptr;
+            const unsigned char *bt = P.dllr ? nullptr : P.bits + o;
+            const float in = P.inv_nbits;
             float dmu = 0.f, drho = 0.f;
-            if (P.Q == 2) user_llr_adjoint<1>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
-            else if (P.Q == 4) user_llr_adjoint<2>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
-            else user_llr_adjoint<3>(Lbar, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
+            if (P.Q == 2) user_llr_adjoint<1>(Lbar, bt, in, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
+            else if (P.Q == 4) user_llr_adjoint<2>(Lbar, bt, in, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
+            else user_llr_adjoint<3>(Lbar, bt, in, zu.x * s, zu.y * s, s, mu, rho, scale, &zbar, &dmu, &drho);
             if (lamK > 0.f) {
                 const float dK = dpK[u].x;   // (g + lambda_K)^-1
                 lamK_bar = fmaf(drho, -gu / (lamK * lamK), lamK_bar);

@@ -37,7 +37,10 @@ struct Params {
     float2 *z_hist;      // [W][S][K][U] or nullptr
     // backward only
     const float2 *zh_in; // [W][S][K][U]
-    const float *dllr;   // [W][S][U][Q]
+    const float *dllr;   // [W][S][U][Q], or nullptr when bits is given
+    const unsigned char *bits;  // [W][S][U][Q] 0/1, or nullptr: the adjoint forms
+                                // dLoss/dLLR itself for the mean BCE of the LLRs
+    float inv_nbits;     // 1 / (W S U Q), with bits
     float2 *dy;          // [W][S][B] or nullptr
     float *partials;     // [nblocks][K + 1]
 };

@@ -115,6 +115,16 @@ def test_backward_workspace_size_and_null_checks(lib):
     assert lib.ocd_detect_backward(ctypes.byref(pb), d, d, None, d, d, None, d, d, d, n, None) == -1
     # workspace too small
     assert lib.ocd_detect_backward(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, 16, None) == -1
+    # the fused cross-entropy form: the same checks, bits in place of dllr
+    lib.ocd_detect_backward_bce.restype = ctypes.c_int
+    lib.ocd_detect_backward_bce.argtypes = lib.ocd_detect_backward.argtypes
+    bce = lib.ocd_detect_backward_bce
+    assert bce(ctypes.byref(pb), d, d, None, d, None, d, d, d, d, n, None) == -1   # no bits
+    assert bce(ctypes.byref(pb), d, d, None, None, d, d, d, d, d, n, None) == -1   # no z_hist
+    assert bce(ctypes.byref(pb), d, d, None, d, d, None, d, d, d, n, None) == -1   # no dlambda
+    assert bce(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, 16, None) == -1     # small workspace
+    assert bce(ctypes.byref(Problem(**dict(_good(), Q=5))), d, d, None, d, d, d, d, d, d, n,
+               None) == -1
 
 
 def test_backward_autotune_rejects_bad_arguments(lib):

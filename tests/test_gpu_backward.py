@@ -172,3 +172,30 @@ def test_autograd_function_drives_the_kernels(ocd):
     assert rel(host(lam.grad), dlam_o) <= GRAD_TOL
     assert rel(host(y.grad), dy_o) <= GRAD_TOL
     assert abs(float(host(beta.grad)[0]) - dbeta_o) <= GRAD_TOL * max(abs(dbeta_o), 1e-12)
+
+
+@pytest.mark.parametrize("mode", ["hybrid", "box", "mmse"])
+def test_fused_cross_entropy_adjoint(ocd, mode):
+    """ocd_detect_backward_bce forms dLoss/dLLR = (sigmoid(L) - bit) / N itself from
+    the bits: the same gradients as the two-step path (torch's sigmoid of the
+    forward LLRs, then ocd_detect_backward), and as the FP64 oracle's reverse mode
+    seeded from the oracle's own LLRs and the same bits."""
+    c = _case(ocd, mode)
+    wl = c["wl"]
+    bits_u8 = torch.from_numpy(wl["bits"].astype(np.uint8)).cuda()
+    dlam, dbeta, dy = ocd.backward(c["H"], c["y"], c["zh"], None, c["K"], c["Q"], mode, c["N0"],
+                                   1.0, c["beta"], lam=c["lam_t"], bits=bits_u8)
+    torch.cuda.synchronize()
+    say("  fused dlam", host(dlam), "two-step", c["dlam"])
+    assert rel(host(dlam), c["dlam"]) <= 1e-4
+    assert rel(host(dy), c["dy"]) <= 1e-4
+    assert abs(float(host(dbeta)[0]) - c["dbeta"]) <= 1e-4 * max(abs(c["dbeta"]), 1e-12)
+    _, Lo = oracle.detect(wl["H"], wl["y"], c["K"], c["Q"], mode, N0=c["N0"], lam=c["lam"],
+                          beta=c["beta"])
+    dllr_o = (scipy.special.expit(Lo) - wl["bits"]) / wl["bits"].size
+    dlam_o, dbeta_o, dy_o = oracle.grad(wl["H"], wl["y"], dllr_o, c["K"], c["Q"], mode,
+                                        N0=c["N0"], lam=c["lam"], beta=c["beta"])
+    assert rel(host(dlam), dlam_o) <= GRAD_TOL
+    assert rel(host(dy), dy_o) <= GRAD_TOL
+    if mode != "mmse":
+        assert abs(float(host(dbeta)[0]) - dbeta_o) <= GRAD_TOL * abs(dbeta_o)
