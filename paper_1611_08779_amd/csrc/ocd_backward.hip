@@ -209,23 +209,23 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
 }
 
 // Sums the per-workgroup partials in a fixed order: thread t adds workgroups
-// t, t + 256, ... sequentially, then a fixed tree over the 256 threads.
+// t, t + 256, ... sequentially, each wave sums its 64 lanes with a fixed
+// cross-lane tree, and the four wave sums are added in a fixed order (one
+// barrier in all, against eight for a tree through LDS).
 __global__ __launch_bounds__(256) void k_reduce_partials(const float *partials, int nblocks, int K,
                                                          int box, float *dlambda, float *dbeta)
 {
-    __shared__ float red[256];
+    __shared__ float red[4];
     const int e = blockIdx.x;   // 0..K-1: dlambda, K: dbeta
     float s = 0.f;
     for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(size_t)b * (K + 1) + e];
-    red[threadIdx.x] = s;
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        if (e < K) dlambda[e] = red[0];
-        else *dbeta = box ? red[0] : 0.f;
+        const float t = (red[0] + red[1]) + (red[2] + red[3]);
+        if (e < K) dlambda[e] = t;
+        else *dbeta = box ? t : 0.f;
     }
 }
 
