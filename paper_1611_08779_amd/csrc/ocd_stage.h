@@ -444,12 +444,14 @@ __device__ __forceinline__ float2 coordinate_update(const HT *h, float2 dp, floa
     }
     // r <- r - h Delta with Delta = z_u' - z_u, written with -Delta so that h enters
     // only with positive sign (the inner product above already uses -Im h; a shared
-    // negated copy would cost one instruction per entry).  Same bits as axpy_sub.
-    const float ndr = zo.x - cr, ndi = zo.y - ci, di = ci - zo.y;
+    // negated copy would cost one instruction per entry).  Im Delta = -ndi enters as a
+    // negated operand, which the FMA takes for free (a - b is exactly -(b - a)).
+    // Same bits as axpy_sub.
+    const float ndr = zo.x - cr, ndi = zo.y - ci;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
         r[i].x = fmaf(hre(h[i]), ndr, r[i].x);
-        r[i].x = fmaf(him(h[i]), di, r[i].x);
+        r[i].x = fmaf(him(h[i]), -ndi, r[i].x);
         r[i].y = fmaf(hre(h[i]), ndi, r[i].y);
         r[i].y = fmaf(him(h[i]), ndr, r[i].y);
     }
