@@ -1,6 +1,9 @@
 """Differentiable unfolded OCD: a ``torch.autograd.Function`` around
 ``ocd_detect`` (forward, keeping the per-sweep history of z) and
-``ocd_detect_backward`` (the hand-written adjoint kernel).
+``ocd_detect_backward`` (the hand-written adjoint kernel), and a second one for
+the training loss itself, the mean binary cross-entropy of the LLRs against the
+transmitted bits, whose backward is ``ocd_detect_backward_bce`` (dLoss/dLLR
+formed inside the adjoint kernel).
 
 Learnable quantities: the per-sweep regularisers ``lam`` ([K], the HYBRID
 mode's lambda_k), the box half-width ``beta`` (a one-element tensor) and the
@@ -14,7 +17,7 @@ import torch
 
 from . import (backward as _ocd_backward, detect as _ocd_detect, problem as _problem)
 
-__all__ = ["OCDFunction", "ocd_llr"]
+__all__ = ["OCDFunction", "ocd_llr", "OCDBCEFunction", "ocd_bce_loss"]
 
 
 class OCDFunction(torch.autograd.Function):
@@ -48,6 +51,44 @@ class OCDFunction(torch.autograd.Function):
 def ocd_llr(y, H, K, Q, mode="hybrid", N0=1.0, Es=1.0, lam=None, beta=None, storage="f32"):
     """Differentiable LLRs [W, S, U, Q] of OCD detection (see OCDFunction)."""
     return OCDFunction.apply(y, lam, beta, H, K, Q, mode, N0, Es, storage)
+
+
+class OCDBCEFunction(torch.autograd.Function):
+    """loss = mean over the W S U Q bits of softplus(L) - bit L, L = OCD(y; lam, beta, H):
+    the forward runs ocd_detect and the loss in torch; the backward is one launch of
+    the adjoint with the loss gradient formed from the bits (no dLoss/dLLR array)."""
+
+    @staticmethod
+    def forward(ctx, y, lam, beta, H, bits, K, Q, mode, N0, Es, storage):
+        beta_val = float(beta.detach().reshape(-1)[0].item()) if beta is not None else 0.0
+        lam_c = lam.detach().contiguous().float() if lam is not None else None
+        y_c = y.detach().contiguous()
+        bits_u8 = bits.detach().to(torch.uint8).contiguous()
+        _, llr, z_hist = _ocd_detect(H, y_c, K, Q, mode, N0, Es, beta_val, lam=lam_c,
+                                     storage=storage, want_z=False, want_llr=True, want_hist=True)
+        loss = torch.nn.functional.binary_cross_entropy_with_logits(llr, bits_u8.float())
+        ctx.save_for_backward(y_c, H, z_hist, lam_c, bits_u8)
+        ctx.cfg = (K, Q, mode, N0, Es, beta_val, storage, lam is not None, beta is not None)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        y, H, z_hist, lam, bits = ctx.saved_tensors
+        K, Q, mode, N0, Es, beta_val, storage, has_lam, has_beta = ctx.cfg
+        dlam, dbeta, dy = _ocd_backward(H, y, z_hist, None, K, Q, mode, N0, Es, beta_val, lam=lam,
+                                        storage=storage, want_dy=ctx.needs_input_grad[0],
+                                        bits=bits)
+        gy = dy * grad_loss if ctx.needs_input_grad[0] else None
+        glam = dlam * grad_loss if has_lam and ctx.needs_input_grad[1] else None
+        gbeta = dbeta * grad_loss if has_beta and ctx.needs_input_grad[2] else None
+        return gy, glam, gbeta, None, None, None, None, None, None, None, None
+
+
+def ocd_bce_loss(y, H, bits, K, Q, mode="hybrid", N0=1.0, Es=1.0, lam=None, beta=None,
+                 storage="f32"):
+    """Differentiable mean binary cross-entropy of OCD's LLRs against bits [W, S, U, Q]
+    (0/1, any dtype), P(bit = 1) = sigmoid(L) (see OCDBCEFunction)."""
+    return OCDBCEFunction.apply(y, lam, beta, H, bits, K, Q, mode, N0, Es, storage)
 
 
 def problem_of(y, H, K, Q, mode, N0, Es, beta=0.0, storage="f32"):

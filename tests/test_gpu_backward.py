@@ -199,3 +199,34 @@ def test_fused_cross_entropy_adjoint(ocd, mode):
     assert rel(host(dy), dy_o) <= GRAD_TOL
     if mode != "mmse":
         assert abs(float(host(dbeta)[0]) - dbeta_o) <= GRAD_TOL * abs(dbeta_o)
+
+
+def test_fused_loss_function_matches_llr_function_plus_torch_loss(ocd):
+    """ocd_bce_loss (forward loss in torch, backward through ocd_detect_backward_bce)
+    gives the loss and the gradients of ocd_llr followed by torch's BCE with logits,
+    including a non-unit upstream gradient."""
+    from paper_1611_08779_amd.autograd import ocd_bce_loss, ocd_llr
+    B, U, W, S, Q, K = 128, 16, 16, 4, 4, 4
+    wl = synth.make_workload(B, U, W, S, Q, 10.0, seed=[21, 1])
+    N0 = f32(wl["N0"])
+    H = dev(wl["H"])
+    bits = torch.from_numpy(wl["bits"]).cuda()
+    grads = []
+    for fused in (False, True):
+        y = dev(wl["y"]).requires_grad_(True)
+        lam = torch.full((K,), N0, device="cuda", requires_grad=True)
+        beta = torch.tensor([3 / np.sqrt(10)], device="cuda", dtype=torch.float32,
+                            requires_grad=True)
+        if fused:
+            loss = ocd_bce_loss(y, H, bits, K, Q, "hybrid", N0, 1.0, lam, beta)
+        else:
+            L = ocd_llr(y, H, K, Q, "hybrid", N0, 1.0, lam, beta)
+            loss = torch.nn.functional.binary_cross_entropy_with_logits(L, bits.float())
+        (2.5 * loss).backward()
+        torch.cuda.synchronize()
+        grads.append((float(loss.detach()), host(lam.grad), float(host(beta.grad)[0]), host(y.grad)))
+    (l0, gl0, gb0, gy0), (l1, gl1, gb1, gy1) = grads
+    assert abs(l1 - l0) <= 1e-6 * abs(l0)
+    assert rel(gl1, gl0) <= 1e-4
+    assert rel(gy1, gy0) <= 1e-4
+    assert abs(gb1 - gb0) <= 1e-4 * max(abs(gb0), 1e-12)
