@@ -230,3 +230,41 @@ def test_fused_loss_function_matches_llr_function_plus_torch_loss(ocd):
     assert rel(gl1, gl0) <= 1e-4
     assert rel(gy1, gy0) <= 1e-4
     assert abs(gb1 - gb0) <= 1e-4 * max(abs(gb0), 1e-12)
+
+
+def test_fused_cross_entropy_adjoint_empty_and_fp16(ocd):
+    """The fused adjoint on an empty problem writes zero gradients; with FP16 storage
+    of H and y it gives the two-step path's gradients."""
+    K, Q = 3, 4
+    pb = ocd.problem(64, 4, 0, 2, Q, K, "hybrid", "f32", 0.1, 1.0, 0.7)
+    H = torch.empty(0, 4, 64, dtype=torch.complex64, device="cuda")
+    y = torch.empty(0, 2, 64, dtype=torch.complex64, device="cuda")
+    zh = torch.empty(0, 2, K, 4, dtype=torch.complex64, device="cuda")
+    bits = torch.empty(0, 2, 4, Q, dtype=torch.uint8, device="cuda")
+    lam = torch.full((K,), 0.1, device="cuda")
+    dlam = torch.full((K,), 7.0, device="cuda")
+    dbeta = torch.full((1,), 7.0, device="cuda")
+    ws = torch.empty(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+    ocd.ocd_detect_backward_bce(pb, H, y, lam, zh, bits, dlam, dbeta, None, ws)
+    torch.cuda.synchronize()
+    assert np.all(host(dlam) == 0.0) and host(dbeta)[0] == 0.0
+
+    B, U, W, S = 128, 8, 24, 4
+    wl = synth.make_workload(B, U, W, S, Q, 10.0, seed=[20, 9])
+    N0 = f32(wl["N0"])
+    pairs = lambda a: torch.view_as_real(dev(a)).to(torch.float16).contiguous()
+    H16, y16 = pairs(wl["H"]), pairs(wl["y"])
+    lam = torch.full((K,), N0, device="cuda")
+    beta = f32(0.9 * 3 / np.sqrt(10))
+    _, L, zh = ocd.detect(H16, y16, K, Q, "hybrid", N0, 1.0, beta, lam=lam, storage="f16",
+                          want_z=False, want_hist=True)
+    bits = torch.from_numpy(wl["bits"]).cuda()
+    dllr = (torch.sigmoid(L) - bits.float()) / bits.numel()
+    two = ocd.backward(H16, y16, zh, dllr, K, Q, "hybrid", N0, 1.0, beta, lam=lam, storage="f16")
+    fused = ocd.backward(H16, y16, zh, None, K, Q, "hybrid", N0, 1.0, beta, lam=lam, storage="f16",
+                         bits=bits)
+    torch.cuda.synchronize()
+    assert rel(host(fused[0]), host(two[0])) <= 1e-4
+    assert rel(host(fused[2]), host(two[2])) <= 1e-4
+    assert abs(float(host(fused[1])[0]) - float(host(two[1])[0])) <= \
+        1e-4 * max(abs(float(host(two[1])[0])), 1e-12)
