@@ -206,12 +206,15 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
                 cre = fmin(fmax(cre, -bt), bt);
                 cim = fmin(fmax(cim, -bt), bt);
             }
-            const double dre = cre - zr, dim = cim - zi;
+            // r - round(h (c - z) / 2^11), each component saturated.  The 2^-11 is
+            // folded into (c - z): every product and partial sum is then an integer
+            // times 2^-11 below 2^22, exact in FP64, so the floor sees the same value
+            // as with the scale applied after the sum.
+            const double dre = (cre - zr) * (1.0 / 2048.0), dim = (cim - zi) * (1.0 / 2048.0);
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-                // r - round(h (c - z) / 2^11), each component saturated
-                const double tr = floor(fma(hr[i], dre, fma(-hi[i], dim, 1024.0)) * (1.0 / 2048.0));
-                const double ti = floor(fma(hr[i], dim, fma(hi[i], dre, 1024.0)) * (1.0 / 2048.0));
+                const double tr = floor(fma(hr[i], dre, fma(-hi[i], dim, 0.5)));
+                const double ti = floor(fma(hr[i], dim, fma(hi[i], dre, 0.5)));
                 rr[i] = fx_sat16d(rr[i] - tr);
                 ri[i] = fx_sat16d(ri[i] - ti);
             }
