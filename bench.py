@@ -605,7 +605,8 @@ def mmse_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, errs_ocd, nbits)
     o1 = [(torch.empty(W1, 1, U, dtype=torch.complex64, device=dev),
            torch.empty(W1, 1, U, Q, dtype=torch.float32, device=dev)) for _ in ins]
     plan1 = best_plan(pb1, ins[0], o1[0], [(16, 16, 0), (16, 8, 0), (16, 4, 0), (32, 8, 0),
-                                           (32, 4, 0), (8, 32, 0), (8, 16, 0)])
+                                           (32, 4, 0), (8, 32, 0), (8, 16, 0), (0, 1, 0),
+                                           (0, 1, 1)])
     fns = [(lambda i=i: ocd.ocd_detect_mmse(pb1, ins[i]["H"], ins[i]["y"], o1[i][0], o1[i][1],
                                             plan1)) for i in range(len(ins))]
     t1, _ = time_graph(torch, GraphedSteps(torch, fns), max(200, args.steps // 4), 20)

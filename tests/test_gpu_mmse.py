@@ -174,6 +174,7 @@ def test_rejects_box_and_bad_plans(ocd):
     (16, 1, 9, 5, 4, 6.0),       # one user
     (64, 6, 10, 16, 4, 12.0),    # S = 16: all 32 columns of the matched-filter product
     (512, 8, 3, 1, 6, 15.0),     # the largest B, one symbol
+    (128, 8, 40, 1, 6, 20.0),    # one H per vector at the headline's B and U
     (24, 7, 5, 9, 6, 20.0),      # U = 7, S = 9
 ])
 def test_matrix_core_form(ocd, B, U, W, S, Q, snr):
