@@ -756,6 +756,31 @@ def fwd_bwd_form(torch, np, ocd, synth, dev):
     }
 
 
+def slots_per_launch_form(torch, ocd, synth, dev, pb32, plan):
+    """The headline detection with n slots' subcarriers in one launch (W = 1200 n,
+    n = 1, 2, 4, 8), same plan, graph replays over 4 distinct inputs: how much of a
+    launch is start-up that more work per launch amortises.  The headline value
+    stays one slot per step."""
+    log("form: slots per launch")
+    B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
+    res = {}
+    for n in (1, 2, 4, 8):
+        Wn = W * n
+        pbn = ocd.problem(B, U, Wn, S, Q, K, "mmse", "f32", pb32.N0)
+        ocd.ocd_set_plan(pbn, plan)
+        ins = [synth.make_workload_device(B, U, Wn, S, Q, 20.0, seed=3000 + 10 * n + i, device=dev)
+               for i in range(4)]
+        z = torch.empty(Wn, S, U, dtype=torch.complex64, device=dev)
+        L = torch.empty(Wn, S, U, Q, dtype=torch.float32, device=dev)
+        fns = [(lambda i=i: ocd.ocd_detect(pbn, ins[i]["H"], ins[i]["y"], z=z, llr=L))
+               for i in range(len(ins))]
+        t, _ = time_graph(torch, GraphedSteps(torch, fns), max(100, 800 // n), 20)
+        res[str(n)] = {"us_per_launch": t * 1e6, "us_per_slot": t * 1e6 / n,
+                       "gbps": Wn * S * U * Q / t / 1e9}
+        del ins, z, L
+    return res
+
+
 def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     forms = {}
     B, U, W, S, Q, K = pb32.B, pb32.U, pb32.W, pb32.S, pb32.Q, pb32.K
@@ -799,6 +824,10 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
 
     # ---- explicit MMSE (Sections II-B, II-E): the detector OCD approximates
     forms["exact_mmse"] = mmse_form(torch, ocd, synth, dev, args, slots, pb32, t32, e32, nb)
+
+    # ---- several slots per launch (start-up amortised)
+    forms["slots_per_launch"] = slots_per_launch_form(torch, ocd, synth, dev, pb32,
+                                                      ocd.ocd_get_plan(pb32))
 
     # ---- S = 1: one channel matrix per vector (HBM-bound shape)
     forms["s1_one_H_per_vector"] = s1_form(torch, ocd, synth, dev, args, pb32)
