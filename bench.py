@@ -122,9 +122,12 @@ class GraphedSteps:
         self.g.replay()
 
 
-def time_graph(torch, gs, steps, warmup):
-    """Replays the graph until `steps` steps ran; returns seconds per step."""
-    reps = max(1, math.ceil(steps / gs.n))
+def time_graph(torch, gs, steps, warmup, tail=None):
+    """Replays the graph until `steps` steps ran; returns (seconds per step, steps
+    timed).  Without `tail` the count is rounded up to whole replays; with `tail`, a
+    graph of the first steps % n launches replayed once after the whole ones, it is
+    exactly `steps`.  Warm-up replays whole graphs, at least `warmup` steps."""
+    reps = steps // gs.n if tail is not None else max(1, math.ceil(steps / gs.n))
     for _ in range(max(1, math.ceil(warmup / gs.n))):
         gs.replay()
     torch.cuda.synchronize()
@@ -132,9 +135,12 @@ def time_graph(torch, gs, steps, warmup):
     e0.record()
     for _ in range(reps):
         gs.replay()
+    if tail is not None:
+        tail.replay()
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3 / (reps * gs.n), reps * gs.n
+    n = reps * gs.n + (tail.n if tail is not None else 0)
+    return e0.elapsed_time(e1) / 1e3 / n, n
 
 
 def kernel_durations(torch, fns, rounds=2):
@@ -399,8 +405,10 @@ def main():
     fns = [step_fn(i) for i in range(len(slots))]
     t_single = kernel_durations(torch, fns)
     gs = GraphedSteps(torch, fns)
+    rem = args.steps % len(fns)
+    gs_tail = GraphedSteps(torch, fns[:rem]) if rem else None   # exactly --steps steps
     log("timing %d steps" % args.steps)
-    t_step, nsteps = time_graph(torch, gs, args.steps, args.warmup)
+    t_step, nsteps = time_graph(torch, gs, args.steps, args.warmup, tail=gs_tail)
     # one launch per step: the kernel's average launch duration over the timed
     # region (HIP events on the stream the graph replays on)
     t_kernel = t_step
