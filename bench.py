@@ -897,12 +897,14 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     t_eager = e0.elapsed_time(e1) / reps
     agree = all(torch.allclose(z[j], zs[j], rtol=1e-5, atol=1e-6) for j in range(len(probs)))
     total_bits = sum(p.W * p.S * p.U * p.Q for p in probs)
+    total_flops = sum(algorithmic(p.B, p.U, p.S, p.K, p.Q)[0] * p.W * p.S for p in probs)
     forms["batched_48_jobs"] = {
         "ms_one_launch_graph": t_batched, "ms_one_launch_eager": t_batched_eager,
         "ms_per_job_launches_graph": t_sep,
         "ms_per_job_launches_eager": t_eager,
         "speedup_vs_per_job_graph": t_sep / t_batched, "speedup_vs_per_job_eager": t_eager / t_batched,
         "gbps_one_launch": total_bits / (t_batched / 1e3) / 1e9, "results_agree": bool(agree),
+        "tflops_one_launch": total_flops / (t_batched / 1e3) / 1e12,
         "jobs": len(probs), "vectors": sum(p.W * p.S for p in probs),
     }
     del Hs, ys, z, L, zs, Ls, ws, gs, call
