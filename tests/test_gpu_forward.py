@@ -81,6 +81,14 @@ def test_b128_u8_64qam_full_slot(ocd):
     say("  BER %.4g (64-QAM at 20 dB per-user SNR)" % ber)
 
 
+@pytest.mark.parametrize("plan", [(16, 4, 0, 1), (32, 4, 0, 1)])
+def test_b128_u8_64qam_one_h_per_vector_full_size(ocd, plan):
+    """The S = 1 shape the benchmark times, whole: 16,800 vectors with one channel
+    matrix each (B=128, U=8, 64-QAM, K=3, 20 dB), under the two register plans its
+    autotuner chooses between, against the oracle."""
+    run_and_compare(ocd, 128, 8, 16800, 1, 6, 3, "mmse", 20.0, [2, 5, 0], plan=plan)
+
+
 @pytest.mark.parametrize("plan", [(4, 14, 0), (4, 16, 1), (8, 28, 0), (8, 64, 1), (16, 32, 0)])
 def test_b128_u8_64qam_slice_plans(ocd, plan):
     run_and_compare(ocd, 128, 8, 60, 14, 6, 3, "mmse", 20.0, [2, 1, 0], plan=plan)
