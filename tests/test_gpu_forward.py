@@ -283,6 +283,29 @@ def test_fp16_storage_parity(ocd):
     assert e <= Z_TOL_F16
 
 
+def test_fp16_storage_headline_full_slot(ocd):
+    """The FP16-storage form the benchmark times, whole: B=128, U=8, 1200 x 14, 64-QAM,
+    K=3, MMSE.  Against the oracle on the FP16-rounded inputs (FP32 tolerance) and on
+    the FP32 inputs (3e-3); bit errors within 2% of the FP32 path's on the same noise
+    (at 12 dB, where there are enough)."""
+    B, U, W, S, Q, K = 128, 8, 1200, 14, 6, 3
+    wl = synth.make_workload(B, U, W, S, Q, 12.0, seed=[10, 3])
+    N0 = f32(wl["N0"])
+    H16, y16 = to_f16_pairs(wl["H"]), to_f16_pairs(wl["y"])
+    z, L, _ = ocd.detect(dev(H16), dev(y16), K, Q, "mmse", N0, storage="f16")
+    _, L32, _ = ocd.detect(dev(wl["H"]), dev(wl["y"]), K, Q, "mmse", N0)
+    torch.cuda.synchronize()
+    zo, Lo, _ = oracle_ref(from_f16_pairs(H16), from_f16_pairs(y16), K, Q, "mmse", N0)
+    assert z_rel_err(host(z), zo) <= Z_TOL_F32
+    assert llr_rel_err(host(L), Lo) <= LLR_TOL_F32
+    zo32, _, _ = oracle_ref(wl["H"], wl["y"], K, Q, "mmse", N0)
+    assert z_rel_err(host(z), zo32) <= Z_TOL_F16
+    e16 = int(np.sum((host(L) > 0) != wl["bits"]))
+    e32 = int(np.sum((host(L32) > 0) != wl["bits"]))
+    say("  errors fp32 %d fp16 %d of %d bits" % (e32, e16, wl["bits"].size))
+    assert e32 >= 500 and abs(e16 - e32) <= 0.02 * e32
+
+
 @pytest.mark.parametrize("case", [(128, 8, 60, 14, 6, 3, "mmse"), (33, 5, 7, 3, 4, 2, "box")])
 def test_fp16_storage_shapes(ocd, case):
     B, U, W, S, Q, K, mode = case
