@@ -122,3 +122,27 @@ def test_jobs_tuner_and_fp16_storage(ocd):
         assert z_rel_err(host(z[j]), zo) <= Z_TOL_F32, j
         assert llr_rel_err(host(L[j]), Lo) <= LLR_TOL_F32, j
     ocd.ocd_release_graphs()
+
+
+def test_the_48_job_batch_at_full_size_sampled(ocd):
+    """The batched workload the benchmark times, whole (48 jobs drawn by
+    synth.batched_job_list, 865,200 vectors, one launch with the tuner): three
+    subcarriers (all their symbols) of every job against the oracle."""
+    jl = synth.batched_job_list()
+    probs, Hs, ys = [], [], []
+    for j, jd in enumerate(jl):
+        wl = synth.make_workload_device(jd["B"], jd["U"], jd["W"], jd["S"], jd["Q"], jd["snr_db"],
+                                        seed=3000 + j, device="cuda")
+        probs.append(ocd.problem(jd["B"], jd["U"], jd["W"], jd["S"], jd["Q"], jd["K"], "mmse", "f32",
+                                 f32(wl["N0"])))
+        Hs.append(wl["H"])
+        ys.append(wl["y"])
+    say("jobs: the 48-job batch, %d vectors" % sum(p.W * p.S for p in probs))
+    z, L, _ = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_TUNE)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(48)
+    for j, pb in enumerate(probs):
+        ws = torch.as_tensor(np.sort(rng.choice(pb.W, 3, replace=False)), device="cuda")
+        zo, Lo, _ = oracle_ref(host(Hs[j][ws]), host(ys[j][ws]), pb.K, pb.Q, "mmse", pb.N0)
+        assert z_rel_err(host(z[j][ws]), zo) <= Z_TOL_F32, j
+        assert llr_rel_err(host(L[j][ws]), Lo) <= LLR_TOL_F32, j
