@@ -268,3 +268,29 @@ def test_fused_cross_entropy_adjoint_empty_and_fp16(ocd):
     assert rel(host(fused[2]), host(two[2])) <= 1e-4
     assert abs(float(host(fused[1])[0]) - float(host(two[1])[0])) <= \
         1e-4 * max(abs(float(host(two[1])[0])), 1e-12)
+
+
+def test_fused_adjoint_at_the_full_differentiable_workload(ocd):
+    """The differentiable workload the benchmark times, whole: B=128, U=16, 2048
+    subcarriers x 4 symbols, 16-QAM, K=4, HYBRID, 10 dB, with the fused cross-entropy
+    adjoint; against the oracle's reverse mode seeded from its own LLRs and the bits."""
+    B, U, W, S, Q, K = 128, 16, 2048, 4, 4, 4
+    wl = synth.make_workload(B, U, W, S, Q, 10.0, seed=[20, 11])
+    N0 = f32(wl["N0"])
+    lam = np.full(K, N0, np.float32)
+    beta = f32(3 / np.sqrt(10))
+    H, y = dev(wl["H"]), dev(wl["y"])
+    _, _, zh = ocd.detect(H, y, K, Q, "hybrid", N0, 1.0, beta, lam=dev(lam), want_z=False,
+                          want_hist=True)
+    bits = torch.from_numpy(wl["bits"]).cuda()
+    dlam, dbeta, dy = ocd.backward(H, y, zh, None, K, Q, "hybrid", N0, 1.0, beta, lam=dev(lam),
+                                   bits=bits)
+    torch.cuda.synchronize()
+    _, Lo = oracle.detect(wl["H"], wl["y"], K, Q, "hybrid", N0=N0, lam=lam, beta=beta, threads=0)
+    dllr_o = (scipy.special.expit(Lo) - wl["bits"]) / wl["bits"].size
+    dlam_o, dbeta_o, dy_o = oracle.grad(wl["H"], wl["y"], dllr_o, K, Q, "hybrid", N0=N0, lam=lam,
+                                        beta=beta)
+    say("  dlam gpu", host(dlam), "oracle", dlam_o)
+    assert rel(host(dlam), dlam_o) <= GRAD_TOL
+    assert rel(host(dy), dy_o) <= GRAD_TOL
+    assert abs(float(host(dbeta)[0]) - dbeta_o) <= GRAD_TOL * abs(dbeta_o)
