@@ -304,7 +304,8 @@ ocd_status ocd_detect_fixed(const ocd_problem *pb, const int16_t *H, const int16
  *   x        device [B][S][Ncp + N] complex FP32 (interleaved), each symbol's cyclic
  *            prefix first
  *   y        device [W][S][B] complex FP32, overwritten
- * FP32 arithmetic (Stockham FFT, twiddles rounded from double).  Asynchronous on
+ * FP32 arithmetic (Stockham FFT, twiddles rounded from double).  B S > 2^30:
+ * OCD_EUNSUPPORTED; a failed device query or launch: OCD_EDEVICE.  Asynchronous on
  * `stream`; no allocation. */
 typedef struct {
     int B, S;   /* receive antennas, OFDM symbols */
