@@ -265,7 +265,10 @@ __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, i
         if (live) {
             const float2 *h = sm.H + (size_t)slot * P.slot_stride + (size_t)u * Bpad;
 #pragma unroll
-            for (int b = l16; b < BP; b += 16) acc = fmaf(h[b].x, h[b].x, fmaf(h[b].y, h[b].y, acc));
+            for (int i = 0; i < (BP + 15) / 16; ++i) {   // entries l16, l16 + 16, ... < BP
+                const int b = l16 + 16 * i;
+                if (b < BP) acc = fmaf(h[b].x, h[b].x, fmaf(h[b].y, h[b].y, acc));
+            }
         }
         acc = group_sum<16>(acc);
         if (!live) continue;
