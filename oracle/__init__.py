@@ -48,6 +48,8 @@ def _open(path):
     lib.oracle_detect.argtypes = common + [dp, dp, dp, dp, i]
     lib.oracle_hard.argtypes = common + [dp, dp, ctypes.POINTER(ctypes.c_ubyte)]
     lib.oracle_grad.argtypes = common + [dp, dp, dp, dp, dp, dp]
+    i8 = ctypes.POINTER(ctypes.c_int8)
+    lib.oracle_active_set.argtypes = common + [dp, dp, i8, i8]
     lib.oracle_ocd_trace.argtypes = [i, i, i, i, i, d, d, dp, d, dp, dp, dp]
     lib.oracle_constellation.argtypes = [i, dp, ctypes.POINTER(ctypes.c_uint)]
     lib.oracle_mmse.argtypes = [i, i, i, i, i, d, d, dp, dp, dp, dp, dp, i]
@@ -56,7 +58,7 @@ def _open(path):
     lib.oracle_fx_recip.argtypes = [ctypes.c_int64]
     lib.oracle_fx_recip.restype = ctypes.c_int64
     for f in ("oracle_ocd", "oracle_cd", "oracle_llr", "oracle_detect", "oracle_hard",
-              "oracle_grad", "oracle_ocd_trace", "oracle_constellation", "oracle_mmse",
+              "oracle_grad", "oracle_active_set", "oracle_ocd_trace", "oracle_constellation", "oracle_mmse",
               "oracle_ocd_fixed"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
@@ -211,6 +213,25 @@ def grad(H, y, dllr, K, Q, mode="mmse", N0=1.0, Es=1.0, lam=None, beta=0.0):
     if rc:
         raise ValueError("oracle_grad rejected its arguments")
     return dlam, float(dbeta[0]), dy
+
+
+def active_set(H, y, K, Q, mode="mmse", N0=1.0, Es=1.0, lam=None, beta=0.0):
+    """The pieces of the path in use at these inputs: (clip [W,S,K,U,2] in {-1,0,1}, the
+    side of the box of every projection; amin [W,S,U,Q,2], the two max-log minimisers of
+    every bit).  The loss is smooth across a step that leaves both unchanged."""
+    lib = _load()
+    H, y = _c128(H), _c128(y)
+    W, U, B = H.shape
+    S = y.shape[1]
+    lam = _lam(lam, K)
+    clip = np.zeros((W, S, K, U, 2), np.int8)
+    amin = np.zeros((W, S, U, Q, 2), np.int8)
+    i8 = ctypes.POINTER(ctypes.c_int8)
+    rc = lib.oracle_active_set(*_common(H, S, K, Q, mode, N0, Es, lam, beta), _ptr(H), _ptr(y),
+                               clip.ctypes.data_as(i8), amin.ctypes.data_as(i8))
+    if rc:
+        raise ValueError("oracle_active_set rejected its arguments")
+    return clip, amin
 
 
 def constellation(Q):

@@ -62,7 +62,8 @@
  *                exact-MMSE LLR of Section II-E.  BOX magnitude: unpinned (R3).
  *   oracle_hard  textbook MRC BER for U = 1 QPSK; transmitted bits at high SNR.
  *   oracle_grad  FP64 central finite differences of the oracle's own forward
- *                pass, away from kinks.
+ *                pass, away from kinks (steps across which oracle_active_set
+ *                is unchanged).
  *   oracle_mmse  normal equations (G + lambda I) z = H^H y by matrix products;
  *                a library linear solve; the K -> infinity limit of oracle_ocd;
  *                U = 1 and orthogonal-column closed forms (where the LLRs equal
@@ -213,12 +214,24 @@ static void regularised_gains(const problem *P, const double *g, double *dinv, d
 /* Equalisation, form (ii): Algorithm 1 (OCD) as printed                   */
 /* ---------------------------------------------------------------------- */
 
+/* Which side of the box a pre-projection value lies on, per component: -1
+ * below -beta, +1 above beta, 0 inside (|w| <= beta counts as inside, the
+ * convention of the adjoint, reading C9); always 0 without the box. */
+static void clip_state(const problem *P, cplx w, signed char *out)
+{
+    double c[2] = {creal(w), cimag(w)};
+    for (int i = 0; i < 2; ++i)
+        out[i] = (signed char)(!P->box ? 0 : c[i] > P->beta ? 1 : c[i] < -P->beta ? -1 : 0);
+}
+
 /* One vector.  r starts at y and z at 0 (initialisation); each sweep k and
  * user u computes z_u = proj(d_u^-1 h_u^H r + p_u z_u), the change Delta, and
- * the incremental residual update r <- r - h_u Delta (equation eq:residual). */
+ * the incremental residual update r <- r - h_u Delta (equation eq:residual).
+ * clip (optional, [K][U][2]) receives the side of the box of every projection. */
 static void ocd_one(const problem *P, const cplx *Hw, const cplx *yv,
                     const double *dinv, const double *p,
-                    cplx *r, cplx *z, cplx *hist /* [K][U] or NULL */)
+                    cplx *r, cplx *z, cplx *hist /* [K][U] or NULL */,
+                    signed char *clip /* [K][U][2] or NULL */)
 {
     int B = P->B, U = P->U;
     for (int b = 0; b < B; ++b) r[b] = yv[b];
@@ -228,7 +241,9 @@ static void ocd_one(const problem *P, const cplx *Hw, const cplx *yv,
             const cplx *h = Hw + (size_t)u * B;
             cplx ip = 0.0;
             for (int b = 0; b < B; ++b) ip += conj(h[b]) * r[b];
-            cplx znew = project(P, dinv[k * U + u] * ip + p[k * U + u] * z[u]);
+            cplx c = dinv[k * U + u] * ip + p[k * U + u] * z[u];
+            if (clip) clip_state(P, c, clip + ((size_t)k * U + u) * 2);
+            cplx znew = project(P, c);
             cplx delta = znew - z[u];
             for (int b = 0; b < B; ++b) r[b] -= h[b] * delta;
             z[u] = znew;
@@ -266,7 +281,7 @@ int oracle_ocd(int B, int U, int W, int S, int K, int Q, int mode, double N0, do
                 column_norms(&P, Hw, g);
                 regularised_gains(&P, g, dinv, p);
                 ocd_one(&P, Hw, yc + (size_t)v * B, dinv, p, r, z,
-                        z_hist ? (cplx *)z_hist + (size_t)v * K * U : NULL);
+                        z_hist ? (cplx *)z_hist + (size_t)v * K * U : NULL, NULL);
                 for (int u = 0; u < U; ++u) ((cplx *)z_out)[(size_t)v * U + u] = z[u];
             }
         }
@@ -481,6 +496,57 @@ int oracle_detect(int B, int U, int W, int S, int K, int Q, int mode, double N0,
     if (oracle_ocd(B, U, W, S, K, Q, mode, N0, Es, lambda, beta, H, y, z_out, NULL, threads))
         return -1;
     return oracle_llr(B, U, W, S, K, Q, mode, N0, Es, lambda, beta, H, z_out, llr, threads);
+}
+
+/* The active set of the whole path at these inputs: the pieces of the
+ * piecewise-smooth map from (lambda, beta, y) to the LLRs that are in use.
+ * The loss is differentiable wherever a small change of the inputs leaves
+ * it unchanged, so central finite differences (the check of the reference
+ * gradient) are taken only across steps that leave it unchanged.
+ *   clip [W][S][K][U][2]: side of the box of every projection (clip_state);
+ *   amin [W][S][U][Q][2]: the two max-log minimisers of every bit (maxlog_one),
+ *                         -1 for a user whose LLRs are 0 (reading R6). */
+int oracle_active_set(int B, int U, int W, int S, int K, int Q, int mode, double N0, double Es,
+                      const double *lambda, double beta, const double *H, const double *y,
+                      signed char *clip, signed char *amin)
+{
+    problem P;
+    if (setup(&P, B, U, W, S, K, Q, mode, N0, Es, lambda, beta)) return -1;
+    cplx pts[64];
+    unsigned labels[64];
+    qam_points(Q, pts, labels);
+    const cplx *Hc = (const cplx *)H;
+    const cplx *yc = (const cplx *)y;
+    double *g = malloc(sizeof(double) * U);
+    double *dinv = malloc(sizeof(double) * (size_t)K * U);
+    double *p = malloc(sizeof(double) * (size_t)K * U);
+    cplx *r = malloc(sizeof(cplx) * B);
+    cplx *z = malloc(sizeof(cplx) * U);
+    double Lv[6];
+    int a0[6], a1[6];
+    long nvec = (long)W * S;
+    for (long v = 0; v < nvec; ++v) {
+        const cplx *Hw = Hc + (size_t)(v / S) * U * B;
+        column_norms(&P, Hw, g);
+        regularised_gains(&P, g, dinv, p);
+        ocd_one(&P, Hw, yc + (size_t)v * B, dinv, p, r, z, NULL, clip + (size_t)v * K * U * 2);
+        for (int u = 0; u < U; ++u) {
+            signed char *am = amin + ((size_t)v * U + u) * Q * 2;
+            double mu, rho;
+            gain_sinr(&P, g[u], &mu, &rho);
+            if (!(rho > 0.0) || !(mu > 0.0)) {
+                for (int b = 0; b < 2 * Q; ++b) am[b] = -1;
+                continue;
+            }
+            maxlog_one(Q, pts, labels, z[u] / (mu * sqrt(Es)), rho, Lv, a0, a1);
+            for (int b = 0; b < Q; ++b) {
+                am[2 * b] = (signed char)a0[b];
+                am[2 * b + 1] = (signed char)a1[b];
+            }
+        }
+    }
+    free(g); free(dinv); free(p); free(r); free(z); free(P.lambda);
+    return 0;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -81,6 +81,59 @@ def test_b128_u8_64qam_full_slot(ocd):
     say("  BER %.4g (64-QAM at 20 dB per-user SNR)" % ber)
 
 
+def _full_slot_against_oracle(ocd, pb, wl, want_plan=None):
+    """Detects the whole headline slot with the plan cached for `pb` and compares every
+    vector with the oracle; returns the plan the launch used."""
+    N0 = f32(wl["N0"])
+    H, y = dev(wl["H"]), dev(wl["y"])
+    used = ocd.ocd_get_plan(pb)
+    say("  plan used %s" % used.as_dict())
+    if want_plan is not None:
+        assert (used.lanes_per_vector, used.vectors_per_block, used.xcd_remap,
+                used.channel_in_registers) == want_plan
+    z, L, _ = ocd.detect(H, y, 3, 6, "mmse", N0)
+    torch.cuda.synchronize()
+    zo, Lo, _ = oracle_ref(wl["H"], wl["y"], 3, 6, "mmse", N0)
+    ez, el = z_rel_err(host(z), zo), llr_rel_err(host(L), Lo)
+    say("  z err %.3g  llr err %.3g over %d vectors" % (ez, el, zo.shape[0] * zo.shape[1]))
+    assert ez <= Z_TOL_F32, ez
+    assert el <= LLR_TOL_F32, el
+    return used
+
+
+def test_b128_u8_64qam_full_slot_bench_plan_forced(ocd):
+    """The headline slot whole (16,800 vectors) under the launch plan the benchmark's
+    autotuner picks on MI355X: 16 lanes per vector (8 complex entries per lane), one
+    subcarrier's 14 symbols per workgroup (the dense one-subcarrier staging path),
+    XCD-aware tile order; U = 8 takes the unrolled user loop.  That is the kernel
+    instance k_forward<L=16, NPL=8, FP32, MMSE, U=8>, checked against the oracle."""
+    B, U, W, S, Q, K = 128, 8, 1200, 14, 6, 3
+    say("case headline slot, bench plan (16, 14, 1, 0)")
+    wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[2, 0, 1])
+    pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", f32(wl["N0"]))
+    ocd.ocd_set_plan(pb, ocd.Plan(16, 14, 1, 0))
+    _full_slot_against_oracle(ocd, pb, wl, want_plan=(16, 14, 1, 0))
+
+
+def test_b128_u8_64qam_full_slot_bench_autotuned(ocd):
+    """The headline slot whole under whatever plan the autotuner chooses, tuned exactly
+    as the benchmark tunes it (ocd_autotune on the slot, 5 repeats); the plan used is
+    the one the tuner returned."""
+    B, U, W, S, Q, K = 128, 8, 1200, 14, 6, 3
+    say("case headline slot, autotuned plan")
+    wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[2, 0, 2])
+    N0 = f32(wl["N0"])
+    pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
+    H, y = dev(wl["H"]), dev(wl["y"])
+    z = torch.empty(W, S, U, dtype=torch.complex64, device="cuda")
+    L = torch.empty(W, S, U, Q, dtype=torch.float32, device="cuda")
+    tuned = ocd.ocd_autotune(pb, H, y, z, L, repeats=5)
+    say("  autotuned %s" % tuned.as_dict())
+    _full_slot_against_oracle(ocd, pb, wl, want_plan=(
+        tuned.lanes_per_vector, tuned.vectors_per_block, tuned.xcd_remap,
+        tuned.channel_in_registers))
+
+
 @pytest.mark.parametrize("plan", [(16, 4, 0, 1), (32, 4, 0, 1)])
 def test_b128_u8_64qam_one_h_per_vector_full_size(ocd, plan):
     """The S = 1 shape the benchmark times, whole: 16,800 vectors with one channel
@@ -89,7 +142,8 @@ def test_b128_u8_64qam_one_h_per_vector_full_size(ocd, plan):
     run_and_compare(ocd, 128, 8, 16800, 1, 6, 3, "mmse", 20.0, [2, 5, 0], plan=plan)
 
 
-@pytest.mark.parametrize("plan", [(4, 14, 0), (4, 16, 1), (8, 28, 0), (8, 64, 1), (16, 32, 0)])
+@pytest.mark.parametrize("plan", [(4, 14, 0), (4, 16, 1), (8, 28, 0), (8, 64, 1), (16, 32, 0),
+                                  (16, 14, 1), (16, 14, 0), (16, 28, 1)])
 def test_b128_u8_64qam_slice_plans(ocd, plan):
     run_and_compare(ocd, 128, 8, 60, 14, 6, 3, "mmse", 20.0, [2, 1, 0], plan=plan)
 

@@ -17,6 +17,7 @@ import pytest
 import scipy.linalg
 import scipy.special
 
+import fd_util
 import oracle
 import synth
 
@@ -373,23 +374,26 @@ def _forward_loss(H, y, bits, K, Q, mode, N0, lam, beta):
     return _bce_loss(L, bits)
 
 
-def _fd(fun, x0, h):
-    return (fun(x0 + h) - fun(x0 - h)) / (2 * h)
+def _evaluate(H, y, bits, K, Q, mode, N0, lam, beta):
+    """(mean BCE loss, active set) of the oracle's forward pass."""
+    z = oracle.ocd(H, y, K, Q, mode, N0=N0, lam=lam, beta=beta)
+    L = oracle.llr(H, z, K, Q, mode, N0=N0, lam=lam, beta=beta)
+    return _bce_loss(L, bits), oracle.active_set(H, y, K, Q, mode, N0=N0, lam=lam, beta=beta)
 
 
-def _check_fd(fun, x0, analytic, tol=1e-6):
-    """Central differences at two steps; a coordinate where they disagree sits on a
-    kink (a clip or an argmin switch) and is skipped.  Returns True if compared."""
-    h = 1e-6 * max(1.0, abs(x0))
-    a, b = _fd(fun, x0, h), _fd(fun, x0, h / 2)
-    if abs(a - b) > 1e-7 * max(1.0, abs(b)):
-        return False
-    assert abs(b - analytic) <= tol * max(1e-3, abs(b)), (b, analytic)
-    return True
+def _check(fd, analytic, tol=1e-7):
+    """FP64 central difference against the reverse mode, relative 1e-7 (absolute below
+    1e-3); None = the active set changed across every step: excluded."""
+    if fd is None:
+        return 0
+    assert abs(fd - analytic) <= tol * max(1e-3, abs(fd)), (fd, analytic)
+    return 1
 
 
 @pytest.mark.parametrize("mode", ["hybrid", "mmse", "box"])
 def test_reference_gradient_matches_finite_differences(mode):
+    """Reverse mode (oracle_grad) against FP64 central differences of the forward pass,
+    each taken across a step that leaves the active set unchanged (tests/fd_util.py)."""
     B, U, W, S, K, Q = 12, 3, 2, 2, 3, 4
     wl = synth.make_workload(B, U, W, S, Q, 6.0, seed=[10, K], dtype=np.complex128)
     H, y, bits = wl["H"], wl["y"], wl["bits"]
@@ -406,21 +410,54 @@ def test_reference_gradient_matches_finite_differences(mode):
             def f(v, k=k):
                 l2 = lam.copy()
                 l2[k] = v
-                return _forward_loss(H, y, bits, K, Q, mode, N0, l2, beta)
-            compared += _check_fd(f, lam[k], dlam[k])
+                return _evaluate(H, y, bits, K, Q, mode, N0, l2, beta)
+            compared += _check(fd_util.central(f, lam[k]), dlam[k])
     if mode != "mmse":
-        compared += _check_fd(lambda v: _forward_loss(H, y, bits, K, Q, mode, N0, lam, v),
-                              beta, dbeta)
+        compared += _check(fd_util.central(
+            lambda v: _evaluate(H, y, bits, K, Q, mode, N0, lam, v), beta), dbeta)
         assert dbeta != 0.0
     for (w, s, b) in [(0, 0, 0), (0, 1, 5), (1, 0, 11), (1, 1, 3)]:
         for part in (1.0, 1j):
             def f(v, w=w, s=s, b=b, part=part):
                 y2 = y.copy()
                 y2[w, s, b] += part * v
-                return _forward_loss(H, y2, bits, K, Q, mode, N0, lam, beta)
+                return _evaluate(H, y2, bits, K, Q, mode, N0, lam, beta)
             ana = dy[w, s, b].real if part == 1.0 else dy[w, s, b].imag
-            compared += _check_fd(f, 0.0, ana)
-    assert compared >= 6
+            compared += _check(fd_util.central(f, 0.0), ana)
+    total = (K if lam is not None else 0) + (mode != "mmse") + 8
+    assert compared >= total - 1, (compared, total)   # at most one coordinate on a kink
+
+
+def test_active_set_describes_the_forward_pass():
+    """oracle.active_set against the forward pass it describes: a component recorded as
+    clipped ends the sweep at exactly +-beta on that side, one recorded inside does not
+    sit beyond the box; every LLR equals rho (|x - a0|^2 - |x - a1|^2) with the two
+    recorded minimisers, a0 carrying bit 0 and a1 bit 1."""
+    B, U, W, S, K, Q = 16, 4, 3, 2, 3, 4
+    wl = synth.make_workload(B, U, W, S, Q, 0.0, seed=[10, 7], dtype=np.complex128)
+    H, y, N0 = wl["H"], wl["y"], wl["N0"]
+    beta = 0.5
+    lam = np.array([0.2, 0.1, 0.3])
+    z, zh = oracle.ocd(H, y, K, Q, "hybrid", N0=N0, lam=lam, beta=beta, hist=True)
+    clip, amin = oracle.active_set(H, y, K, Q, "hybrid", N0=N0, lam=lam, beta=beta)
+    parts = np.stack([zh.real, zh.imag], axis=-1)
+    assert np.all(parts[clip == 1] == beta) and np.all(parts[clip == -1] == -beta)
+    assert np.all(np.abs(parts[clip == 0]) <= beta)
+    assert np.any(clip != 0) and np.any(clip == 0)
+    pts, lab = oracle.constellation(Q)
+    L = oracle.llr(H, z, K, Q, "hybrid", N0=N0, lam=lam, beta=beta)
+    g = np.sum(np.abs(H) ** 2, axis=2)                       # [W, U]
+    mu = g / (g + lam[-1])
+    rho = g / lam[-1]
+    x = z / mu[:, None, :]
+    for b in range(Q):
+        a0, a1 = amin[..., b, 0], amin[..., b, 1]
+        assert np.all((lab[a0] >> (Q - 1 - b)) & 1 == 0) and np.all((lab[a1] >> (Q - 1 - b)) & 1 == 1)
+        want = rho[:, None, :] * (np.abs(x - pts[a0]) ** 2 - np.abs(x - pts[a1]) ** 2)
+        np.testing.assert_allclose(L[..., b], want, rtol=1e-12, atol=1e-12)
+    # box mode without a regulariser: every projection clips or not, LLR minimisers exist
+    clip_b, amin_b = oracle.active_set(H, y, K, Q, "box", N0=N0, beta=beta)
+    assert np.all(amin_b >= 0) and set(np.unique(clip_b)) <= {-1, 0, 1}
 
 
 @pytest.mark.parametrize("mode", ["mmse", "box"])
