@@ -122,23 +122,34 @@ class GraphedSteps:
         self.g.replay()
 
 
+WARM_SECONDS = 0.25   # sustained load before timing: the GPU's clocks ramp up under load
+
+
 def time_graph(torch, gs, steps, warmup, tail=None):
     """Replays the graph until `steps` steps ran; returns (seconds per step, steps
     timed).  Without `tail` the count is rounded up to whole replays; with `tail`, a
     graph of the first steps % n launches replayed once after the whole ones, it is
-    exactly `steps`.  Warm-up replays whole graphs, at least `warmup` steps, and the
-    tail once (a graph's first replay uploads it).  The start event follows a short
-    spin kernel, during which the host queues every timed launch: the events then
-    bracket the steps' GPU time, not the host's submission of the first graph."""
+    exactly `steps`.
+
+    Warm-up: whole-graph replays until at least `warmup` steps ran and at least
+    WARM_SECONDS passed (a few milliseconds of load leave the clocks below their
+    sustained level: the same kernel runs ~10% longer in the first milliseconds),
+    and the tail once (a graph's first replay uploads it).  One more untimed replay
+    runs right before the start event with nothing synchronised after it, so the host
+    queues every timed launch while the GPU is busy: the events bracket exactly the
+    timed steps' GPU time."""
     reps = steps // gs.n if tail is not None else max(1, math.ceil(steps / gs.n))
-    for _ in range(max(1, math.ceil(warmup / gs.n))):
-        gs.replay()
+    t0, done = time.perf_counter(), 0
+    while done < warmup or time.perf_counter() - t0 < WARM_SECONDS:
+        for _ in range(max(1, math.ceil(warmup / gs.n))):
+            gs.replay()
+            done += gs.n
+        torch.cuda.synchronize()
     if tail is not None:
         tail.replay()
-        gs.replay()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda._sleep(SPIN_CYCLES)
+    gs.replay()
     e0.record()
     for _ in range(reps):
         gs.replay()
@@ -148,9 +159,6 @@ def time_graph(torch, gs, steps, warmup, tail=None):
     torch.cuda.synchronize()
     n = reps * gs.n + (tail.n if tail is not None else 0)
     return e0.elapsed_time(e1) / 1e3 / n, n
-
-
-SPIN_CYCLES = 2_000_000   # a few hundred microseconds of GPU time before the start event
 
 
 def kernel_durations(torch, fns, rounds=2):
@@ -310,7 +318,16 @@ def summarize_profile(dirs, traffic_out, command):
             counters.setdefault(cname, {}).setdefault(_kernel_key(r), []).append(
                 float(_col(r, "Counter_Value")))
     traffic = {}
+    per_kernel = {}   # (kernel shape) -> {counter: median}
     for cname, per in sorted(counters.items()):
+        if cname not in ("FETCH_SIZE", "WRITE_SIZE"):
+            out.append("%s (per dispatch, summed over the device's instances):" % cname)
+            for key, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+                med = statistics.median(v)
+                per_kernel.setdefault(key, {})[cname] = med
+                out.append("  %-58s grid=%-8d wg=%-4d n=%-4d median=%.6g" % (
+                    key[0][:58], key[1], key[2], len(v), med))
+            continue
         # calibration: the largest copy kernel dispatch is the 256 MiB copy
         copies = [(max(v), k) for k, v in per.items() if "copyBuffer" in k[0] or "copy" in k[0].lower()]
         cal = max(copies)[0] if copies else None
@@ -323,6 +340,23 @@ def summarize_profile(dirs, traffic_out, command):
                 name[:58], grid, wg, len(v), med, med * 1024 * (scale or 0) / 1e6))
             if "k_forward" in name:
                 traffic.setdefault(cname, []).append((len(v), name, grid, wg, med, scale))
+    for (name, grid, wg), c in sorted(per_kernel.items()):
+        if "SQ_INSTS_VALU" not in c or "SQ_WAVES" not in c or not c["SQ_WAVES"]:
+            continue
+        out.append("derived, %s grid=%d wg=%d:" % (name[:58], grid, wg))
+        out.append("  VALU instructions per wave %.1f" % (c["SQ_INSTS_VALU"] / c["SQ_WAVES"]))
+        if "SQ_INSTS_VALU_FMA_F32" in c:
+            out.append("  FP32 FMA share of VALU instructions %.3f" % (
+                c["SQ_INSTS_VALU_FMA_F32"] / c["SQ_INSTS_VALU"]))
+        if "SQ_ACTIVE_INST_VALU" in c and "GRBM_GUI_ACTIVE" in c and c["GRBM_GUI_ACTIVE"]:
+            # SQ_ACTIVE_INST_VALU: quad-cycles, summed over waves; GRBM_GUI_ACTIVE: GPU
+            # cycles summed over the 8 XCDs; 1024 SIMDs
+            simd_cycles = c["GRBM_GUI_ACTIVE"] / 8.0 * 1024
+            out.append("  VALU busy (active VALU cycles over SIMD cycles) %.3f" % (
+                4.0 * c["SQ_ACTIVE_INST_VALU"] / simd_cycles))
+            out.append("  GPU cycles per dispatch (per XCD) %.0f" % (c["GRBM_GUI_ACTIVE"] / 8.0))
+        if "SQ_WAVE_CYCLES" in c:
+            out.append("  wave cycles per wave %.0f" % (c["SQ_WAVE_CYCLES"] / c["SQ_WAVES"]))
     print("\n".join(out))
     if traffic_out:
         if "FETCH_SIZE" not in traffic or "WRITE_SIZE" not in traffic:
@@ -771,7 +805,7 @@ def fwd_bwd_form(torch, np, ocd, synth, dev):
     dlam = torch.empty(K5, device=dev)
     dbeta = torch.empty(1, device=dev)
     dy = torch.empty(W5, S5, B5, dtype=torch.complex64, device=dev)
-    wsb = torch.empty(ocd.ocd_backward_workspace_bytes(pb5), dtype=torch.uint8, device=dev)
+    wsb = torch.zeros(ocd.ocd_backward_workspace_bytes(pb5), dtype=torch.uint8, device=dev)
     bits = wl["bits"].float()
     inv_n = 1.0 / bits.numel()
     nbits_s = bits * -inv_n          # -bit / N, fixed labels

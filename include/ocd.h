@@ -61,7 +61,8 @@ typedef enum {
     OCD_OK = 0,
     OCD_EINVAL = -1,       /* bad shape, scalar or pointer */
     OCD_EUNSUPPORTED = -2, /* valid problem this build does not handle (e.g. LDS too small) */
-    OCD_EDEVICE = -3       /* HIP runtime error */
+    OCD_EDEVICE = -3,      /* HIP runtime error */
+    OCD_ESCRATCH = -4      /* problem too large for the static scratch of a no-allocation entry point */
 } ocd_status;
 
 typedef enum { OCD_MMSE = 0, OCD_BOX = 1, OCD_HYBRID = 2 } ocd_mode;
@@ -113,7 +114,8 @@ ocd_status ocd_detect(const ocd_problem *pb, const void *H, const void *y, const
                       const float *g, const float *dinv, const float *p,
                       float *z, float *llr, float *z_hist, hipStream_t stream);
 
-/* Bytes of device workspace ocd_detect_backward needs for this problem. */
+/* Bytes of device workspace ocd_detect_backward needs for this problem: 256 bytes
+ * holding a completion counter, then K + 1 partial sums per workgroup. */
 size_t ocd_backward_workspace_bytes(const ocd_problem *pb);
 
 /* Adjoint of ocd_detect with respect to the per-sweep regularisers, the box
@@ -129,8 +131,14 @@ size_t ocd_backward_workspace_bytes(const ocd_problem *pb);
  *   dlambda     device [K]  dLoss/dlambda_k (overwritten)
  *   dbeta       device [1]  dLoss/dbeta (overwritten; 0 in MMSE mode)
  *   dy          device [W][S][B] complex FP32, dLoss/dRe y + j dLoss/dIm y (may be NULL)
- *   workspace   device, >= ocd_backward_workspace_bytes(pb) bytes, 16-byte aligned
- * dlambda and dbeta are reduced in a fixed order: repeated calls give identical bits.
+ *   workspace   device, >= ocd_backward_workspace_bytes(pb) bytes, 16-byte aligned,
+ *               owned by the caller.  Its first 4 bytes are the adjoint's completion
+ *               counter: they must be zero before the first call with this workspace
+ *               (allocate it zeroed) and every call leaves them zero again, so a
+ *               workspace is reused without clearing.  Calls that share a workspace
+ *               must not overlap in time (same stream, or ordered by events).
+ * dlambda and dbeta are reduced in a fixed order (the last workgroup to finish sums
+ * every workgroup's partials in workgroup order): repeated calls give identical bits.
  * Subgradient conventions: a component of z_u' strictly inside (-beta, beta) is
  * unclipped and one at +-beta clipped (c exactly at +-beta, where the projection's
  * derivative is one-sided, has measure zero); the max-log minimisers are the first
@@ -155,6 +163,35 @@ ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void *H, const v
                                    const float *lambda, const float *z_hist, const uint8_t *bits,
                                    float *dlambda, float *dbeta, float *dy,
                                    void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Capacity, per GPU, of the static device scratch of ocd_detect_backward_bce_noalloc. */
+#define OCD_NOALLOC_SCRATCH_BYTES (1u << 20)
+
+/* ocd_detect_backward_bce for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving or training loops, harnesses that forbid hipMalloc.
+ * The same adjoint and the same kernels, with the completion counter and the
+ * per-workgroup partial sums in a static device array of OCD_NOALLOC_SCRATCH_BYTES,
+ * which the library holds on every GPU it runs on until the process ends, instead of a
+ * caller workspace.  It calls no hipMalloc, hipFree or other allocating routine, and
+ * its host side allocates nothing (if OCD_TUNE_CACHE is set, the first plan lookup of
+ * the process reads that file: make any other call first where even that is not
+ * allowed).
+ *   Size limit: 256 + nblocks (K + 1) 4 bytes <= OCD_NOALLOC_SCRATCH_BYTES, where
+ *               nblocks = ceil(W S / vectors_per_block) of the adjoint's plan for the
+ *               shape (ocd_autotune_backward's cached plan, else the heuristic one).
+ *               Larger problems return OCD_ESCRATCH with nothing launched: use
+ *               ocd_detect_backward_bce with a workspace.
+ *   stream      must belong to the current device (else OCD_EINVAL).
+ * Every call on one GPU shares that GPU's scratch, which keeps the last call's partial
+ * sums: calls that overlap in time on one GPU (several streams or host threads) race
+ * and give wrong gradients, so serialise them.  The counter is zero when the library
+ * loads and every call leaves it zero.  Arguments, outputs and conventions are
+ * otherwise those of ocd_detect_backward_bce, whose results it reproduces bit for bit
+ * under the same plan. */
+ocd_status ocd_detect_backward_bce_noalloc(const ocd_problem *pb, const void *H, const void *y,
+                                           const float *lambda, const float *z_hist,
+                                           const uint8_t *bits, float *dlambda, float *dbeta,
+                                           float *dy, hipStream_t stream);
 
 /* A launch plan: how vectors map onto lanes and workgroups.
  *   lanes_per_vector      lanes that share one (subcarrier, symbol) vector: 4, 8, 16 or 32

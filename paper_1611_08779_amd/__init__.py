@@ -50,7 +50,8 @@ OCD_JOBS_GRAPH = 1
 OCD_JOBS_TUNE = 2
 OCD_JOBS_PERSISTENT = 4
 
-_STATUS = {0: "OCD_OK", -1: "OCD_EINVAL", -2: "OCD_EUNSUPPORTED", -3: "OCD_EDEVICE"}
+_STATUS = {0: "OCD_OK", -1: "OCD_EINVAL", -2: "OCD_EUNSUPPORTED", -3: "OCD_EDEVICE",
+           -4: "OCD_ESCRATCH"}
 
 
 class Problem(ctypes.Structure):
@@ -108,6 +109,7 @@ def _load():
         "ocd_backward_workspace_bytes": ([P], sz),
         "ocd_detect_backward": ([P, vp, vp, fp, fp, fp, fp, fp, fp, vp, sz, vp], ctypes.c_int),
         "ocd_detect_backward_bce": ([P, vp, vp, fp, fp, vp, fp, fp, fp, vp, sz, vp], ctypes.c_int),
+        "ocd_detect_backward_bce_noalloc": ([P, vp, vp, fp, fp, vp, fp, fp, fp, vp], ctypes.c_int),
         "ocd_get_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_set_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_autotune": ([P, vp, vp, fp, fp, ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
@@ -263,6 +265,25 @@ def ocd_detect_backward_bce(pb: Problem, H, y, lam, z_hist, bits, dlam, dbeta, d
         _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
         _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, _stream(stream))
     _check("ocd_detect_backward_bce", st)
+
+
+def ocd_detect_backward_bce_noalloc(pb: Problem, H, y, lam, z_hist, bits, dlam, dbeta, dy,
+                                    stream=None) -> None:
+    """ocd_detect_backward_bce with its scratch in the library's static device array
+    instead of a workspace (for callers that cannot allocate device memory)."""
+    dev = H.device
+    f32 = (torch.float32,)
+    zt = (torch.complex64, torch.float32)
+    st = _lib.ocd_detect_backward_bce_noalloc(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(z_hist, "z_hist", zt, pb.W * pb.S * pb.K * pb.U * 8, dev),
+        _dev_ptr(bits, "bits", (torch.uint8,), pb.W * pb.S * pb.U * pb.Q, dev),
+        _dev_ptr(dlam, "dlam", f32, pb.K * 4, dev),
+        _dev_ptr(dbeta, "dbeta", f32, 4, dev),
+        _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev), _stream(stream))
+    _check("ocd_detect_backward_bce_noalloc", st)
 
 
 def ocd_get_plan(pb: Problem) -> Plan:
@@ -449,7 +470,7 @@ def backward(H, y, z_hist, dllr, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, la
     dlam = torch.empty(K, device=dev, dtype=torch.float32)
     dbeta = torch.empty(1, device=dev, dtype=torch.float32)
     dy = torch.empty(W, S, B, device=dev, dtype=torch.complex64) if want_dy else None
-    ws = torch.empty(ocd_backward_workspace_bytes(pb), device=dev, dtype=torch.uint8)
+    ws = torch.zeros(ocd_backward_workspace_bytes(pb), device=dev, dtype=torch.uint8)   # counter starts at 0
     if dllr is None:
         ocd_detect_backward_bce(pb, H, y, lam, z_hist, bits, dlam, dbeta, dy, ws, stream)
     else:

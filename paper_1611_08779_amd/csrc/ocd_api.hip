@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <string_view>
 #include <vector>
 
 #include "../../include/ocd.h"
@@ -29,6 +30,9 @@ extern "C" const char *ocd_status_str(int status)
     case OCD_EINVAL: return "OCD_EINVAL: invalid argument";
     case OCD_EUNSUPPORTED: return "OCD_EUNSUPPORTED: problem not supported by this build";
     case OCD_EDEVICE: return "OCD_EDEVICE: HIP runtime error";
+    case OCD_ESCRATCH:
+        return "OCD_ESCRATCH: problem too large for the static scratch of the no-allocation "
+               "entry point (use the workspace form)";
     default: return "unknown ocd_status";
     }
 }
@@ -72,25 +76,26 @@ int lds_limit_bytes()
     return limit;
 }
 
-// gfx architecture of the current device (queried once per device).
-std::string arch_name()
+// gfx architecture of the current device, queried once per device into a static
+// table, so that a lookup never allocates.
+const char *arch_name()
 {
     static std::mutex mu;
-    static std::map<int, std::string> names;
+    static char names[MAX_DEVICES][32];
+    static bool known[MAX_DEVICES];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return "unknown";
     std::lock_guard<std::mutex> lk(mu);
-    auto it = names.find(dev);
-    if (it != names.end()) return it->second;
-    hipDeviceProp_t prop;
-    std::string a = "unknown";
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
-        a = prop.gcnArchName;
-        size_t c = a.find(':');
-        if (c != std::string::npos) a = a.substr(0, c);
+    if (!known[dev]) {
+        hipDeviceProp_t prop;
+        std::snprintf(names[dev], sizeof names[dev], "unknown");
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            std::snprintf(names[dev], sizeof names[dev], "%s", prop.gcnArchName);
+            if (char *c = std::strchr(names[dev], ':')) *c = 0;
+        }
+        known[dev] = true;
     }
-    names[dev] = a;
-    return a;
+    return names[dev];
 }
 
 float box_edge(int Q)
@@ -147,7 +152,7 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
     P.sqEs = std::sqrt(pb->Es);
     P.qscale = qam_scale(pb->Q);
     P.invU = 1.0f / (float)pb->U;
-    P.invS = 1.0 / (double)pb->S;
+    set_divisor((unsigned)pb->S, P.divS_m, P.divS_s1, P.divS_s2);
     P.lambda = lambda;
     const long nvec = (long)pb->W * pb->S;
     P.nblocks = (int)((nvec + P.vpb - 1) / P.vpb);
@@ -195,10 +200,12 @@ ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backwar
     ocd_plan best = {L, 1, 0, 0};
     double best_score = -1;
     const int cap = 512 / L;
-    std::vector<int> cands;
-    for (int v = cap; v >= 1; v /= 2) cands.push_back(v);
-    for (int m = pb->S; m <= cap; m += pb->S) cands.push_back(m);
-    for (int v : cands) {
+    int cands[160];   // at most 8 powers of two and 128 multiples of S
+    int nc = 0;
+    for (int v = cap; v >= 1; v /= 2) cands[nc++] = v;
+    for (int m = pb->S; m <= cap; m += pb->S) cands[nc++] = m;
+    for (int i = 0; i < nc; ++i) {
+        const int v = cands[i];
         ocd_plan pl = {L, v, 0, 0};
         Params P;
         int npl, threads;
@@ -216,16 +223,16 @@ ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backwar
 // ------------------------------------------------------------------ plan cache
 
 static std::mutex g_plan_mu;
-static std::map<std::string, ocd_plan> g_plans;
+static std::map<std::string, ocd_plan, std::less<>> g_plans;   // lookups take a string_view
 static bool g_plans_loaded = false;
 
-std::string plan_key(const ocd_problem *pb, bool per_sweep, bool backward)
+PlanKey plan_key(const ocd_problem *pb, bool per_sweep, bool backward)
 {
-    char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|%s|B%d|U%d|W%d|S%d|K%d|Q%d|m%d|s%d|l%d", arch_name().c_str(),
+    PlanKey k;
+    std::snprintf(k.s, sizeof k.s, "%s|%s|B%d|U%d|W%d|S%d|K%d|Q%d|m%d|s%d|l%d", arch_name(),
                   backward ? "bwd" : "fwd", pb->B, pb->U, pb->W, pb->S, pb->K, pb->Q, pb->mode,
                   pb->storage, per_sweep ? 1 : 0);
-    return buf;
+    return k;
 }
 
 static void load_plan_file_locked()
@@ -266,21 +273,21 @@ static void save_plan_file_locked()
     std::rename(tmp.c_str(), path);
 }
 
-bool cached_plan(const std::string &key, ocd_plan &pl)
+bool cached_plan(const PlanKey &key, ocd_plan &pl)
 {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     load_plan_file_locked();
-    auto it = g_plans.find(key);
+    auto it = g_plans.find(std::string_view(key.s));
     if (it == g_plans.end()) return false;
     pl = it->second;
     return true;
 }
 
-void store_plan(const std::string &key, const ocd_plan &pl, bool persist)
+void store_plan(const PlanKey &key, const ocd_plan &pl, bool persist)
 {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     load_plan_file_locked();
-    g_plans[key] = pl;
+    g_plans[std::string(key.s)] = pl;
     if (persist) save_plan_file_locked();
 }
 
@@ -411,7 +418,7 @@ static bool make_mmse_mfma_params(const ocd_problem *pb, const ocd_plan &pl, Par
     P.sqEs = std::sqrt(pb->Es);
     P.qscale = qam_scale(pb->Q);
     P.invU = 1.0f / (float)pb->U;
-    P.invS = 1.0 / (double)pb->S;
+    set_divisor((unsigned)pb->S, P.divS_m, P.divS_s1, P.divS_s2);
     lds = mmse_mfma_lds_bytes(P.Bpad, pb->U, pb->S);
     return lds <= (size_t)lds_limit_bytes();
 }
@@ -569,9 +576,10 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
 extern "C" size_t ocd_backward_workspace_bytes(const ocd_problem *pb)
 {
     if (validate(pb) != OCD_OK) return 0;
-    // block partials of (dlambda_1..K, dbeta) for the plan with the most blocks
+    // the completion ticket (256 bytes), then the block partials of
+    // (dlambda_1..K, dbeta) for the plan with the most blocks
     const long nvec = (long)pb->W * pb->S;
-    return (size_t)std::max(1L, nvec) * (size_t)(pb->K + 1) * sizeof(float) + 256;
+    return 256 + (size_t)std::max(1L, nvec) * (size_t)(pb->K + 1) * sizeof(float);
 }
 
 namespace ocd {
@@ -609,14 +617,18 @@ static ocd_status run_backward(const ocd_problem *pb, const ocd_plan &pl, const 
     P.bits = dllr ? nullptr : bits;
     P.inv_nbits = (float)(1.0 / ((double)pb->W * pb->S * pb->U * pb->Q));
     P.dy = reinterpret_cast<float2 *>(dy);
-    P.partials = reinterpret_cast<float *>(workspace);
+    // workspace: the completion ticket in the first 256 bytes, then the partials
+    P.ticket = reinterpret_cast<unsigned *>(workspace);
+    P.partials = reinterpret_cast<float *>(static_cast<unsigned char *>(workspace) + 256);
+    P.dlambda = dlambda;
+    P.dbeta = dbeta;
     set_vec_ok(P, pb, H, y);
-    hipError_t e = hipSuccess;
-    if (pb->W > 0)
+    hipError_t e;
+    if (pb->W > 0) {
         e = launch_backward(pl.lanes_per_vector, npl, pb->storage == OCD_STORE_F16, P, threads,
                             lds, stream);
-    if (e == hipSuccess) {
-        if (pb->W == 0) P.nblocks = 0;
+    } else {
+        P.nblocks = 0;   // no workgroups: zero gradients
         e = launch_reduce_partials(P, dlambda, dbeta, stream);
     }
     return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
@@ -648,6 +660,68 @@ extern "C" ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void 
     if (st != OCD_OK) return st;
     return run_backward(pb, choose_plan(pb, lambda, true), H, y, lambda, z_hist, nullptr, dlambda,
                         dbeta, dy, workspace, stream, bits);
+}
+
+// ------------------------------------------------------------------ adjoint without allocation
+
+// Scratch of ocd_detect_backward_bce_noalloc: the adjoint's completion counter (first
+// 256 bytes) and its per-workgroup partial sums.  A file-scope device array: every GPU
+// the library runs on holds its own copy, zero when the code object loads, until the
+// process ends.  On the host its name stands in for the symbol and is not a device
+// address: host code uses only the per-device address from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[OCD_NOALLOC_SCRATCH_BYTES];
+
+namespace ocd {
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[MAX_DEVICES];
+
+// Device address of the scratch on device dev (the current device), looked up once
+// per device.
+static ocd_status scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return OCD_EDEVICE;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return OCD_OK;
+}
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_detect_backward_bce_noalloc(const ocd_problem *pb, const void *H,
+                                                      const void *y, const float *lambda,
+                                                      const float *z_hist, const uint8_t *bits,
+                                                      float *dlambda, float *dbeta, float *dy,
+                                                      hipStream_t stream)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!dlambda || !dbeta) return OCD_EINVAL;
+    if (pb->W > 0 && (!H || !y || !z_hist || !bits)) return OCD_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return OCD_EDEVICE;
+    if (dev < 0 || dev >= MAX_DEVICES) return OCD_EUNSUPPORTED;
+    if (stream) {
+        hipDevice_t sdev = 0;
+        if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return OCD_EDEVICE;
+        if (sdev != dev) return OCD_EINVAL;
+    }
+    const ocd_plan pl = choose_plan(pb, lambda, true);
+    Params P;
+    int npl, threads;
+    size_t lds;
+    if (!make_params(pb, pl, lambda, true, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
+    const size_t need = 256 + (size_t)P.nblocks * (size_t)(pb->K + 1) * sizeof(float);
+    if (need > OCD_NOALLOC_SCRATCH_BYTES) return OCD_ESCRATCH;
+    void *ws = nullptr;
+    st = scratch_address(dev, &ws);
+    if (st != OCD_OK) return st;
+    return run_backward(pb, pl, H, y, lambda, z_hist, nullptr, dlambda, dbeta, dy, ws, stream,
+                        bits);
 }
 
 extern "C" ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const void *y,

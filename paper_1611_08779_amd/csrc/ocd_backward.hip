@@ -16,8 +16,12 @@
 // product, one 2-float all-reduce and one axpy: the work of a forward update.
 // A component of z_new equal to +-beta counts as clipped (c exactly at +-beta,
 // where the projection's derivative is one-sided, has measure zero).
-// Per-sweep and box partial sums go to a per-workgroup slot of the workspace
-// and are reduced in a fixed order by k_reduce_partials.
+// Per-sweep and box partial sums go to a per-workgroup slot of the workspace.
+// The last workgroup to finish (a completion ticket taken with one device-scope
+// atomic from a vector lane) sums them in workgroup order and writes dlambda and
+// dbeta: a fixed order, so the gradients are bitwise reproducible, and no second
+// launch (finish_partials; the partials travel through the caches, not the L2s).  The ticket counts to the number of workgroups and is set back to zero
+// by that last workgroup, so it is zero again after every launch.
 #include "ocd_stage.h"
 
 namespace ocd {
@@ -61,7 +65,102 @@ __device__ __forceinline__ void user_llr_adjoint(const float *Lbar, const unsign
     *drho = gr;
 }
 
-template <int L, int NPL, bool F16, bool BOX>
+// Cross-workgroup hand-off of the partial sums.  The L2 caches of the XCDs are not
+// coherent with each other, and a device-scope release fence would write back a
+// whole L2 (every dirty line, the adjoint's dy included) once per workgroup.  Only
+// the K + 1 partials need to travel, so they bypass the caches instead: they are
+// written with device-scope atomic stores (through to the device's coherence
+// point), the store is waited for (vmcnt 0) before the ticket is taken, and the last
+// workgroup reads them with device-scope atomic loads (through the caches) after
+// its ticket returned.
+constexpr int WAIT_VMEM_ONLY = 0x0F70;   // s_waitcnt vmcnt(0), expcnt and lgkmcnt not waited
+
+__device__ __forceinline__ void store_partial(float *p, float v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float load_partial(const float *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The last workgroup to take the completion ticket sums every workgroup's K + 1
+// partials in workgroup order (thread t adds workgroups t, t + blockDim, ...;
+// the waves' lanes by a fixed DPP tree; the waves in order), writes dlambda and
+// dbeta, and resets the ticket.  Every thread of the workgroup must call it after
+// storing its share of the workgroup's partials with store_partial.
+__device__ void finish_partials(const Params &P, int K)
+{
+    __shared__ int last;
+    __shared__ float red[8][8];   // [entry of the batch][wave], at most 8 waves
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(WAIT_VMEM_ONLY);   // this thread's partial stores performed
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned t = __hip_atomic_fetch_add(P.ticket, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        last = t == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_s_waitcnt(WAIT_VMEM_ONLY);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int E = K + 1, nb = gridDim.x;
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int e0 = 0; e0 < E; e0 += 8) {
+        float acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            const float *pb = P.partials + (size_t)b * E + e0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (e0 + i < E) acc[i] += load_partial(pb + i);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = wave_sum(acc[i]);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) red[i][wave] = acc[i];
+        __syncthreads();
+        const int e = e0 + (int)threadIdx.x;
+        if (threadIdx.x < 8 && e < E) {
+            float t = 0.f;
+            for (int w = 0; w < nwaves; ++w) t += red[threadIdx.x][w];
+            if (e < K) P.dlambda[e] = t;
+            else *P.dbeta = P.box ? t : 0.f;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(P.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One adjoint coordinate update (the reverse of update (k, u)): returns the new
+// z_bar_u, accumulates lambda_bar_k and beta_bar, and adds h d^-1 c_bar to r_bar.
+// h: this lane's part of column u; dp = (d_u^-1, p_u); zn = z_u after the update;
+// zbu = z_bar_u before.
+template <int L, int NPL, bool BOX>
+__device__ __forceinline__ float2 adjoint_update(const float2 *h, float2 dp, float2 zn, float2 zbu,
+                                                 float beta, float2 *rb, float &lam_bar,
+                                                 float &beta_bar)
+{
+    const float2 hb = group_sum2<L>(partial_inner<NPL, 2>(h, rb));   // h^H r_bar
+    const float tr = zbu.x - hb.x, ti = zbu.y - hb.y;                // z_bar + Delta_bar
+    float cbr = tr, cbi = ti;
+    if constexpr (BOX) {
+        if (!(fabsf(zn.x) < beta)) { beta_bar += zn.x > 0.f ? tr : -tr; cbr = 0.f; }
+        if (!(fabsf(zn.y) < beta)) { beta_bar += zn.y > 0.f ? ti : -ti; cbi = 0.f; }
+    }
+    lam_bar = fmaf(-dp.x, fmaf(zn.x, cbr, zn.y * cbi), lam_bar);
+    axpy_add<NPL>(h, make_float2(dp.x * cbr, dp.x * cbi), rb);
+    return make_float2(hb.x + dp.y * cbr, hb.y + dp.y * cbi);       // -Delta_bar + p c_bar
+}
+
+// UC > 0: U == UC and the user loop is unrolled: every LDS address of an update is
+// a compile-time offset from one base, and the straight-line sweep lets the
+// compiler read the next column while the current update computes.
+template <int L, int NPL, bool F16, bool BOX, int UC>
 __global__ __launch_bounds__(512) void k_backward(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -131,9 +230,13 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     for (int i = 0; i < NPL; ++i) rb[i] = make_float2(0.f, 0.f);
     const float beta = P.beta;
     float beta_bar = 0.f;
-    float *part_out = P.partials + (size_t)bid * (K + 1);
-
     const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    // per-wave partial of sweep k, parked in LDS until the end
+    auto park_sweep = [&](int k, float lam_bar) {
+        const float ws = wave_sum(active && j == 0 ? lam_bar : 0.f);
+        if ((threadIdx.x & 63) == 0) sm.part[k * nwaves + wave] = ws;
+    };
+
     // z^(k) rows: lane j owns users j, j + L, ...; with U <= ZPL * L the row of the
     // next sweep is loaded into registers while the current sweep computes
     constexpr int ZPL = 4;
@@ -166,38 +269,29 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
         __builtin_amdgcn_wave_barrier();   // z^(k) row written by its owner lanes
         const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
         float lam_bar = (k == K - 1) ? lamK_bar : 0.f;
-        for (int u = U - 1; u >= 0; --u) {
-            float2 h[NPL];
-            load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
-            float2 hb = partial_inner<NPL, 2>(h, rb);
-            hb.x = group_sum<L>(hb.x);
-            hb.y = group_sum<L>(hb.y);
-            const float2 dp = dpk[u], zn = zv[u], zbu = zb[u];
-            const float tr = zbu.x - hb.x, ti = zbu.y - hb.y;   // z_bar + Delta_bar
-            float cbr = tr, cbi = ti;
-            if constexpr (BOX) {
-                if (!(fabsf(zn.x) < beta)) { beta_bar += zn.x > 0.f ? tr : -tr; cbr = 0.f; }
-                if (!(fabsf(zn.y) < beta)) { beta_bar += zn.y > 0.f ? ti : -ti; cbi = 0.f; }
+        if constexpr (UC > 0) {
+            constexpr int BP = L * NPL;   // = Bpad: the columns are BP apart
+#pragma unroll
+            for (int u = UC - 1; u >= 0; --u) {
+                float2 h[NPL];
+                load_column<L, NPL>(Hs + u * BP, j, h);
+                zb[u] = adjoint_update<L, NPL, BOX>(h, dpk[u], zv[u], zb[u], beta, rb, lam_bar,
+                                                    beta_bar);
             }
-            lam_bar = fmaf(-dp.x, fmaf(zn.x, cbr, zn.y * cbi), lam_bar);
-            zb[u] = make_float2(hb.x + dp.y * cbr, hb.y + dp.y * cbi);   // -Delta_bar + p c_bar
-            axpy_add<NPL>(h, make_float2(dp.x * cbr, dp.x * cbi), rb);
+        } else {
+            for (int u = U - 1; u >= 0; --u) {
+                float2 h[NPL];
+                load_column<L, NPL>(Hs + (size_t)u * Bpad, j, h);
+                zb[u] = adjoint_update<L, NPL, BOX>(h, dpk[u], zv[u], zb[u], beta, rb, lam_bar,
+                                                    beta_bar);
+            }
         }
-        // per-wave partial of sweep k, parked in LDS until the end
-        const float ws = wave_sum(active && j == 0 ? lam_bar : 0.f);
-        if ((threadIdx.x & 63) == 0) sm.part[k * nwaves + wave] = ws;
+        park_sweep(k, lam_bar);
         __builtin_amdgcn_wave_barrier();
     }
     {
         const float ws = wave_sum(active && j == 0 ? beta_bar : 0.f);
         if ((threadIdx.x & 63) == 0) sm.part[K * nwaves + wave] = ws;
-    }
-    __syncthreads();
-    // the workgroup's partials: waves summed in order (fixed order, reproducible)
-    for (int e = threadIdx.x; e <= K; e += blockDim.x) {
-        float sum = 0.f;
-        for (int w = 0; w < nwaves; ++w) sum += sm.part[e * nwaves + w];
-        part_out[e] = sum;
     }
     if (active && P.dy) {
 #pragma unroll
@@ -206,12 +300,21 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
             if (b < P.B) P.dy[(long)v * P.B + b] = rb[i];
         }
     }
+    __syncthreads();
+    // the workgroup's partials: waves summed in order (fixed order, reproducible)
+    float *part_out = P.partials + (size_t)bid * (K + 1);
+    for (int e = threadIdx.x; e <= K; e += blockDim.x) {
+        float sum = 0.f;
+        for (int w = 0; w < nwaves; ++w) sum += sm.part[e * nwaves + w];
+        store_partial(part_out + e, sum);
+    }
+    finish_partials(P, K);
 }
 
-// Sums the per-workgroup partials in a fixed order: thread t adds workgroups
-// t, t + 256, ... sequentially, each wave sums its 64 lanes with a fixed
-// cross-lane tree, and the four wave sums are added in a fixed order (one
-// barrier in all, against eight for a tree through LDS).
+// Writes dlambda and dbeta from nblocks per-workgroup partials in a fixed order
+// (thread t adds workgroups t, t + 256, ...; fixed cross-lane tree; waves in
+// order).  The adjoint kernel reduces its own partials; this kernel writes the
+// zero gradients of an empty problem (nblocks = 0).
 __global__ __launch_bounds__(256) void k_reduce_partials(const float *partials, int nblocks, int K,
                                                          int box, float *dlambda, float *dbeta)
 {
@@ -229,10 +332,10 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float *partials, 
     }
 }
 
-template <int L, int NPL, bool F16, bool BOX>
-static hipError_t launch_bwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
+template <int L, int NPL, bool F16, bool BOX, int UC>
+static hipError_t launch_bwd_u(const Params &p, int threads, size_t lds, hipStream_t s)
 {
-    auto fn = k_backward<L, NPL, F16, BOX>;
+    auto fn = k_backward<L, NPL, F16, BOX, UC>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -240,6 +343,17 @@ static hipError_t launch_bwd_t(const Params &p, int threads, size_t lds, hipStre
     }
     hipLaunchKernelGGL(fn, dim3(p.nblocks), dim3(threads), lds, s, p);
     return hipGetLastError();
+}
+
+// Exactly 8 or 16 users with at most 8 entries per lane take the unrolled user loop.
+template <int L, int NPL, bool F16, bool BOX>
+static hipError_t launch_bwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
+{
+    if constexpr (NPL <= 8) {
+        if (p.U == 8) return launch_bwd_u<L, NPL, F16, BOX, 8>(p, threads, lds, s);
+        if (p.U == 16) return launch_bwd_u<L, NPL, F16, BOX, 16>(p, threads, lds, s);
+    }
+    return launch_bwd_u<L, NPL, F16, BOX, 0>(p, threads, lds, s);
 }
 
 template <int L, int NPL>

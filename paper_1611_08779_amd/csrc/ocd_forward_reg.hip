@@ -47,8 +47,9 @@ __device__ __forceinline__ void reg_load(const Params &P, int vb, int grp, int j
         x.r[2 * c + 1] = make_float2(q.z, q.w);
     }
     // subcarriers of vb and of this group's vector
-    const int wb = (int)fma((double)vb, P.invS, 0.5 * P.invS);
-    const int w = (int)fma((double)(vb + (active ? grp : 0)), P.invS, 0.5 * P.invS);
+    const int wb = (int)divide_invariant((unsigned)vb, P.divS_m, P.divS_s1, P.divS_s2);
+    const int w = (int)divide_invariant((unsigned)(vb + (active ? grp : 0)), P.divS_m, P.divS_s1,
+                                        P.divS_s2);
     const unsigned char *hb =
         static_cast<const unsigned char *>(P.H) + (size_t)wb * U * B * cbytes<F16>();
     const int wrow = (w - wb) * U;

@@ -25,7 +25,8 @@ struct Params {
     float sqEs;          // sqrt(Es)
     float qscale;        // level spacing of the unit-energy square QAM
     float invU;          // 1 / U (slot of a staged H row without an integer divide)
-    double invS;         // 1 / S (slot of a vector without an integer divide)
+    unsigned divS_m;     // n / S = divide_invariant(n, divS_m, divS_s1, divS_s2) (see
+    int divS_s1, divS_s2;// set_divisor): exact, with no integer divide on the GPU
     const float *lambda; // device [K] or nullptr
     const void *H;       // [W][U][B] complex (FP32 or FP16 pairs)
     const void *y;       // [W][S][B]
@@ -43,7 +44,30 @@ struct Params {
     float inv_nbits;     // 1 / (W S U Q), with bits
     float2 *dy;          // [W][S][B] or nullptr
     float *partials;     // [nblocks][K + 1]
+    unsigned *ticket;    // completion ticket of the adjoint's workgroups (zero between launches)
+    float *dlambda;      // [K] adjoint output
+    float *dbeta;        // [1] adjoint output
 };
+
+// Unsigned 32-bit division by a divisor d fixed for a launch, as a multiply-high,
+// an add and two shifts (Granlund and Montgomery, "Division by invariant integers
+// using multiplication", 1994, the round-up method for all 32-bit dividends):
+// with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1,
+//   t = mulhi(m, n),  n / d = (t + ((n - t) >> min(l, 1))) >> max(l - 1, 0).
+inline void set_divisor(unsigned d, unsigned &m, int &s1, int &s2)
+{
+    int l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    m = (unsigned)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+    s1 = l < 1 ? l : 1;
+    s2 = l > 1 ? l - 1 : 0;
+}
+
+__host__ __device__ inline unsigned divide_invariant(unsigned n, unsigned m, int s1, int s2)
+{
+    const unsigned t = (unsigned)(((unsigned long long)m * n) >> 32);
+    return (t + ((n - t) >> s1)) >> s2;
+}
 
 // Bytes of dynamic LDS a launch of this shape needs.
 inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward, int nwaves = 0)

@@ -58,12 +58,11 @@ struct Tile {
 };
 
 // Staged slot of lane group grp's vector: (vbase + grp) / S - w_first, from the
-// offset of the group in its first subcarrier (below 2^30): in double precision
-// (x + 1/2) / S is within 1/(2S) of an integer plus one half, so truncation is exact.
+// offset of the group in its first subcarrier (non-negative, below 2^31).
 __device__ __forceinline__ int slot_of_group(const Params &P, const Tile &tile, int grp)
 {
     const int x = tile.vbase - tile.w_first * P.S + grp;
-    return (int)fma((double)x, P.invS, 0.5 * P.invS);
+    return (int)divide_invariant((unsigned)x, P.divS_m, P.divS_s1, P.divS_s2);
 }
 
 __device__ __forceinline__ Tile tile_of(const Params &P, int bid)

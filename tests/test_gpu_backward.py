@@ -191,7 +191,7 @@ def test_backward_autotuner_keeps_the_gradients(ocd):
     dlam = torch.empty(K, device="cuda")
     dbeta = torch.empty(1, device="cuda")
     dy = torch.empty(W, S, B, dtype=torch.complex64, device="cuda")
-    ws = torch.empty(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+    ws = torch.zeros(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
     plan = ocd.ocd_autotune_backward(pb, c["H"], c["y"], c["lam_t"], c["zh"], c["dllr_t"], dlam,
                                      dbeta, dy, ws, repeats=1)
     say("  tuned adjoint plan", plan.as_dict())
@@ -297,7 +297,7 @@ def test_fused_cross_entropy_adjoint_empty_and_fp16(ocd):
     lam = torch.full((K,), 0.1, device="cuda")
     dlam = torch.full((K,), 7.0, device="cuda")
     dbeta = torch.full((1,), 7.0, device="cuda")
-    ws = torch.empty(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+    ws = torch.zeros(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
     ocd.ocd_detect_backward_bce(pb, H, y, lam, zh, bits, dlam, dbeta, None, ws)
     torch.cuda.synchronize()
     assert np.all(host(dlam) == 0.0) and host(dbeta)[0] == 0.0
