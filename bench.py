@@ -161,6 +161,15 @@ def time_graph(torch, gs, steps, warmup, tail=None):
     return e0.elapsed_time(e1) / 1e3 / n, n
 
 
+def warm_up(torch, fn):
+    """Runs fn until WARM_SECONDS of sustained load have passed (then synchronises)."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < WARM_SECONDS:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
+
+
 def kernel_durations(torch, fns, rounds=2):
     """Average time of single eager launches: HIP events around each launch on the
     stream it runs on (torch's current stream).  The queue is empty before each
@@ -348,13 +357,14 @@ def summarize_profile(dirs, traffic_out, command):
         if "SQ_INSTS_VALU_FMA_F32" in c:
             out.append("  FP32 FMA share of VALU instructions %.3f" % (
                 c["SQ_INSTS_VALU_FMA_F32"] / c["SQ_INSTS_VALU"]))
-        if "SQ_ACTIVE_INST_VALU" in c and "GRBM_GUI_ACTIVE" in c and c["GRBM_GUI_ACTIVE"]:
-            # SQ_ACTIVE_INST_VALU: quad-cycles, summed over waves; GRBM_GUI_ACTIVE: GPU
-            # cycles summed over the 8 XCDs; 1024 SIMDs
-            simd_cycles = c["GRBM_GUI_ACTIVE"] / 8.0 * 1024
+        if "SQ_ACTIVE_INST_VALU" in c and "SQ_BUSY_CYCLES" in c and c["SQ_BUSY_CYCLES"]:
+            # SQ_ACTIVE_INST_VALU: quad-cycles, summed over waves; SQ_BUSY_CYCLES: cycles
+            # with waves present, summed over the 32 shader engines (8 XCDs x 4); 1024
+            # SIMDs.  (GRBM_GUI_ACTIVE spans more than the kernel under counter collection.)
+            se_cycles = c["SQ_BUSY_CYCLES"] / 32.0
+            out.append("  shader-engine busy cycles per dispatch %.0f" % se_cycles)
             out.append("  VALU busy (active VALU cycles over SIMD cycles) %.3f" % (
-                4.0 * c["SQ_ACTIVE_INST_VALU"] / simd_cycles))
-            out.append("  GPU cycles per dispatch (per XCD) %.0f" % (c["GRBM_GUI_ACTIVE"] / 8.0))
+                4.0 * c["SQ_ACTIVE_INST_VALU"] / (se_cycles * 1024)))
         if "SQ_WAVE_CYCLES" in c:
             out.append("  wave cycles per wave %.0f" % (c["SQ_WAVE_CYCLES"] / c["SQ_WAVES"]))
     print("\n".join(out))
@@ -391,8 +401,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 256 MiB device copy first (counter calibration under rocprofv3)")
     ap.add_argument("--plan", default=None,
-                    help="L,VPB[,XCD]: fix the launch plan instead of autotuning (profiled runs, "
-                         "so that every traced launch of the kernel is the timed one)")
+                    help="L,VPB[,XCD[,STAGGER]]: fix the launch plan instead of autotuning "
+                         "(profiled runs, so that every traced launch of the kernel is the timed one)")
     ap.add_argument("--mmse-only", default=None, metavar="L,VPB",
                     help="only the explicit-MMSE detector on the headline slots with this plan "
                          "(profiled runs); prints its own JSON line")
@@ -485,8 +495,8 @@ def main():
                           "hbm_frac": nbytes * W * S / t / 1e9 / HBM_PEAK_GBPS}), flush=True)
         return
     if args.plan:
-        f = [int(x) for x in args.plan.split(",")] + [0]
-        plan = ocd.Plan(f[0], f[1], f[2], 0)
+        f = [int(x) for x in args.plan.split(",")] + [0, 0]
+        plan = ocd.Plan(f[0], f[1], f[2], 0, f[3])
         ocd.ocd_set_plan(pb, plan)
         log("fixed plan %s" % plan.as_dict())
     else:
@@ -948,11 +958,12 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
         ys.append(wl["y"])
     z, L, ws = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_TUNE)
     torch.cuda.synchronize()
+    schedule = ocd.ocd_jobs_schedule(probs)
+    log("batched jobs: tuned schedule %s" % schedule)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     reps = 20
     call = ocd.JobsCall(probs, Hs, ys, z, L, ws, flags=ocd.OCD_JOBS_GRAPH)
-    call()
-    torch.cuda.synchronize()
+    warm_up(torch, call)
     ev[0].record()
     for _ in range(reps):
         call()
@@ -975,6 +986,7 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     fns = [(lambda j=j: ocd.ocd_detect(probs[j], Hs[j], ys[j], z=zs[j], llr=Ls[j]))
            for j in range(len(probs))]
     gs = GraphedSteps(torch, fns)
+    warm_up(torch, gs.replay)
     ev[2].record()
     for _ in range(reps):
         gs.replay()
@@ -1001,6 +1013,12 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
         "gbps_one_launch": total_bits / (t_batched / 1e3) / 1e9, "results_agree": bool(agree),
         "tflops_one_launch": total_flops / (t_batched / 1e3) / 1e12,
         "jobs": len(probs), "vectors": sum(p.W * p.S for p in probs),
+        "schedule": {"persistent": bool(schedule["persistent"]),
+                     "tile_policy": ["512/L vectors", "whole subcarriers", "half-size"][
+                         schedule["tile_policy"]],
+                     "lane_mode": ["8 entries per lane", "16 per lane for B > 128",
+                                   "16 for B > 128, 4 for 32 < B <= 128"][schedule["lane_mode"]],
+                     "chosen_by": "ocd_detect_jobs' batch tuner (OCD_JOBS_TUNE)"},
     }
     del Hs, ys, z, L, zs, Ls, ws, gs, call
 

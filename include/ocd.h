@@ -204,12 +204,18 @@ ocd_status ocd_detect_backward_bce_noalloc(const ocd_problem *pb, const void *H,
  *                         symbols share H_w); 1: each vector's lane group keeps the
  *                         columns of its H_w in registers and nothing is staged (the
  *                         choice when few do).  1 needs U <= 8 and
- *                         B <= 8 * lanes_per_vector, and is forward-only. */
+ *                         B <= 8 * lanes_per_vector, and is forward-only.
+ *   stagger               0..16, LDS-staged plans: workgroup b waits
+ *                         max(0, b / 128 - 1) * stagger * 512 clocks before it loads
+ *                         its tile, so that the workgroups dispatched first get their
+ *                         data first and start computing while later ones load
+ *                         (0: every workgroup loads at once). */
 typedef struct {
     int lanes_per_vector;
     int vectors_per_block;
     int xcd_remap;
     int channel_in_registers;
+    int stagger;
 } ocd_plan;
 
 /* The plan ocd_detect would use for this problem (cached or heuristic). */
@@ -252,10 +258,17 @@ ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const voi
  *               hipGraph on the first call for this workspace and job list, and
  *               replay it afterwards (job pointers are read from the workspace,
  *               so a change of pointers only re-uploads the tables).
- *               OCD_JOBS_TUNE: before running, time every schedule and tile-size
- *               policy on the caller's buffers (outputs are overwritten;
- *               synchronises `stream`) and keep the fastest for this list of shapes.
+ *               OCD_JOBS_TUNE: before running, time every schedule, tile-size
+ *               policy and lane mode on the caller's buffers (outputs are
+ *               overwritten; synchronises `stream`) and keep the fastest for this
+ *               list of shapes.
  *               OCD_JOBS_PERSISTENT: use the persistent schedule.
+ *               OCD_JOBS_LANE_MODE(m), m = 0, 1, 2: use lane mode m (below)
+ *               instead of the tuned one.
+ * Lane modes (complex entries per lane, NPL; a job's lanes per vector are B / NPL):
+ *   0: NPL = 8 for every job;  1: NPL = 16 for jobs with B > 128, else 8;
+ *   2: as 1, and NPL = 4 for jobs with 32 < B <= 128.
+ * A job whose (lanes, NPL) pair the kernel is not built for keeps NPL = 8.
  * When the tables change, the call enqueues a host-to-device copy of them from
  * pinned memory held by the library and first waits for the previous copy from
  * the same workspace, so it may block until earlier work on `stream` consumed
@@ -263,10 +276,20 @@ ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const voi
 #define OCD_JOBS_GRAPH 1
 #define OCD_JOBS_TUNE 2
 #define OCD_JOBS_PERSISTENT 4
+#define OCD_JOBS_LANE_MODE_SHIFT 4
+#define OCD_JOBS_LANE_MODE(m) (((m) + 1) << OCD_JOBS_LANE_MODE_SHIFT)
 size_t ocd_jobs_workspace_bytes(const ocd_problem *jobs, int n_jobs);
 ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const *H, const void *const *y,
                            float *const *z, float *const *llr, int n_jobs,
                            void *workspace, size_t workspace_bytes, int flags, hipStream_t stream);
+
+/* The schedule ocd_detect_jobs runs for this list of shapes: the one the last
+ * OCD_JOBS_TUNE call chose, else the default (one workgroup per tile, tiles of
+ * whole subcarriers, lane mode 0).  Outputs (host): persistent (0 or 1, before the
+ * OCD_JOBS_PERSISTENT flag is applied), tile_policy (0: tiles of 512 / L vectors,
+ * 1: whole subcarriers, 2: half-size tiles) and lane_mode (above). */
+ocd_status ocd_jobs_schedule(const ocd_problem *jobs, int n_jobs, int *persistent,
+                             int *tile_policy, int *lane_mode);
 
 /* Explicit MMSE soft-output detection, the baseline that OCD approximates without
  * forming the Gram matrix (Section II-B: regularised Gram matrix and its inverse;

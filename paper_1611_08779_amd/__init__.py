@@ -38,7 +38,7 @@ __all__ = [
     "problem", "detect", "preprocess", "backward", "detect_jobs", "detect_mmse", "detect_fixed",
     "OCD_JOBS_GRAPH",
     "OCD_JOBS_TUNE",
-    "OCD_JOBS_PERSISTENT", "JobsCall",
+    "OCD_JOBS_PERSISTENT", "OCD_JOBS_LANE_MODE", "JobsCall", "ocd_jobs_schedule",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +49,11 @@ STORAGES = {"f32": 0, "f16": 1}
 OCD_JOBS_GRAPH = 1
 OCD_JOBS_TUNE = 2
 OCD_JOBS_PERSISTENT = 4
+
+
+def OCD_JOBS_LANE_MODE(m):
+    """ocd_detect_jobs flag: run lane mode m (0, 1, 2) instead of the tuned one."""
+    return (m + 1) << 4
 
 _STATUS = {0: "OCD_OK", -1: "OCD_EINVAL", -2: "OCD_EUNSUPPORTED", -3: "OCD_EDEVICE",
            -4: "OCD_ESCRATCH"}
@@ -69,17 +74,18 @@ class Problem(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    """``ocd_plan``: lanes per vector, vectors per workgroup, XCD remap, and whether
+    """``ocd_plan``: lanes per vector, vectors per workgroup, XCD remap, whether
     each vector keeps its channel columns in registers instead of sharing an
-    LDS-staged H_w."""
+    LDS-staged H_w, and the staggering of the staged loads."""
 
     _fields_ = [("lanes_per_vector", ctypes.c_int), ("vectors_per_block", ctypes.c_int),
-                ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int)]
+                ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int),
+                ("stagger", ctypes.c_int)]
 
     def as_dict(self):
         return {"lanes_per_vector": self.lanes_per_vector,
                 "vectors_per_block": self.vectors_per_block, "xcd_remap": self.xcd_remap,
-                "channel_in_registers": self.channel_in_registers}
+                "channel_in_registers": self.channel_in_registers, "stagger": self.stagger}
 
 
 class OfdmShape(ctypes.Structure):
@@ -119,6 +125,9 @@ def _load():
         "ocd_detect_jobs": ([P, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(vp), ctypes.c_int, vp, sz, ctypes.c_int, vp], ctypes.c_int),
         "ocd_release_graphs": ([], None),
+        "ocd_jobs_schedule": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+                              ctypes.c_int),
         "ocd_detect_mmse": ([P, vp, vp, fp, fp, ctypes.POINTER(Plan), vp], ctypes.c_int),
         "ocd_detect_fixed": ([P, vp, vp, vp, fp, vp], ctypes.c_int),
         "ocd_ofdm_demodulate": ([ctypes.POINTER(OfdmShape), vp, vp, vp], ctypes.c_int),
@@ -412,6 +421,16 @@ class JobsCall:
 
 def ocd_detect_jobs(jobs, H, y, z, llr, workspace, flags=0, stream=None) -> None:
     JobsCall(jobs, H, y, z, llr, workspace, flags)(stream=stream)
+
+
+def ocd_jobs_schedule(jobs) -> dict:
+    """The schedule ocd_detect_jobs runs for this list of shapes (the tuned one, else
+    the default): persistent or one workgroup per tile, tile policy, lane mode."""
+    arr = _problem_array(jobs)
+    pers, pol, mode = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check("ocd_jobs_schedule", _lib.ocd_jobs_schedule(arr, len(jobs), ctypes.byref(pers),
+                                                       ctypes.byref(pol), ctypes.byref(mode)))
+    return {"persistent": pers.value, "tile_policy": pol.value, "lane_mode": mode.value}
 
 
 def ocd_release_graphs() -> None:

@@ -37,7 +37,7 @@ extern "C" const char *ocd_status_str(int status)
     }
 }
 
-extern "C" int ocd_version(void) { return 10000; }
+extern "C" int ocd_version(void) { return 10100; }
 
 // ------------------------------------------------------------------ validation
 
@@ -98,6 +98,22 @@ const char *arch_name()
     return names[dev];
 }
 
+int device_cu_count()
+{
+    static std::mutex mu;
+    static int cus[MAX_DEVICES];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cus[dev] <= 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 float box_edge(int Q)
 {
     const int M = 1 << (Q / 2);
@@ -131,6 +147,7 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
     npl = npl_for(pb->B, L);
     if (!npl) return false;
     if (pl.channel_in_registers < 0 || pl.channel_in_registers > 1) return false;
+    if (pl.stagger < 0 || pl.stagger > 16) return false;
     const bool reg = pl.channel_in_registers != 0;
     if (reg && (backward || (L != 16 && L != 32) || !reg_user_bound(pb->U, npl))) return false;
     const int cap = (reg ? 256 : 512) / L;
@@ -146,6 +163,7 @@ bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda,
     const int row = P.U * P.Bpad;             // float2 per slot, before padding
     P.slot_stride = row + ((row % 16 == 0) ? 8 : (16 - row % 16 + 8) % 16);
     P.xcd_remap = pl.xcd_remap ? 1 : 0;
+    P.stagger = pl.stagger;
     P.Es = pb->Es; P.N0 = pb->N0;
     P.beta = pb->beta > 0.f ? pb->beta : box_edge(pb->Q) * std::sqrt(pb->Es);
     P.lam_default = pb->mode == OCD_BOX ? 0.f : pb->N0 / pb->Es;
@@ -246,13 +264,13 @@ static void load_plan_file_locked()
     char line[512];
     while (std::fgets(line, sizeof line, f)) {
         char key[256];
-        ocd_plan pl = {0, 0, 0, 0};
-        if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"lanes_per_vector\": %d, "
-                              "\"vectors_per_block\": %d, \"xcd_remap\": %d, "
-                              "\"channel_in_registers\": %d",
-                        key, &pl.lanes_per_vector, &pl.vectors_per_block, &pl.xcd_remap,
-                        &pl.channel_in_registers) == 5)
-            g_plans[key] = pl;
+        ocd_plan pl = {0, 0, 0, 0, 0};
+        const int n = std::sscanf(line, " {\"key\": \"%255[^\"]\", \"lanes_per_vector\": %d, "
+                                        "\"vectors_per_block\": %d, \"xcd_remap\": %d, "
+                                        "\"channel_in_registers\": %d, \"stagger\": %d",
+                                  key, &pl.lanes_per_vector, &pl.vectors_per_block, &pl.xcd_remap,
+                                  &pl.channel_in_registers, &pl.stagger);
+        if (n >= 5) g_plans[key] = pl;   // files written before the stagger field: 0
     }
     std::fclose(f);
 }
@@ -266,9 +284,9 @@ static void save_plan_file_locked()
     if (!f) return;
     for (auto &kv : g_plans)
         std::fprintf(f, "{\"key\": \"%s\", \"lanes_per_vector\": %d, \"vectors_per_block\": %d, "
-                        "\"xcd_remap\": %d, \"channel_in_registers\": %d}\n",
+                        "\"xcd_remap\": %d, \"channel_in_registers\": %d, \"stagger\": %d}\n",
                      kv.first.c_str(), kv.second.lanes_per_vector, kv.second.vectors_per_block,
-                     kv.second.xcd_remap, kv.second.channel_in_registers);
+                     kv.second.xcd_remap, kv.second.channel_in_registers, kv.second.stagger);
     std::fclose(f);
     std::rename(tmp.c_str(), path);
 }
@@ -560,6 +578,23 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best_ms) { best_ms = ms; best_pl = pl; }
     }
+    // second stage: the staggered staging on the fastest LDS-staged plan
+    if (st == OCD_OK && !best_pl.channel_in_registers) {
+        const ocd_plan base = best_pl;
+        for (int sg : {1, 2, 4}) {
+            ocd_plan pl = base;
+            pl.stagger = sg;
+            (void)hipEventRecord(e0, stream);
+            for (int i = 0; i < repeats && st == OCD_OK; ++i)
+                st = run_forward(pb, pl, H, y, nullptr, nullptr, nullptr, nullptr, z, llr,
+                                 nullptr, stream);
+            (void)hipEventRecord(e1, stream);
+            if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) { st = OCD_EDEVICE; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best_pl = pl; }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != OCD_OK) return st;
@@ -775,6 +810,23 @@ extern "C" ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best_ms) { best_ms = ms; best_pl = pl; }
+    }
+    // second stage: the staggered staging on the fastest plan
+    if (st == OCD_OK) {
+        const ocd_plan base = best_pl;
+        for (int sg : {1, 2, 4}) {
+            ocd_plan pl = base;
+            pl.stagger = sg;
+            (void)hipEventRecord(e0, stream);
+            for (int i = 0; i < repeats && st == OCD_OK; ++i)
+                st = run_backward(pb, pl, H, y, lambda, z_hist, dllr, dlambda, dbeta, dy,
+                                  workspace, stream);
+            (void)hipEventRecord(e1, stream);
+            if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) { st = OCD_EDEVICE; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best_pl = pl; }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

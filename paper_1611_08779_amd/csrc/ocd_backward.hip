@@ -170,6 +170,7 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     const Smem sm = carve(smem, P, vpb_cap, true);
     const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const Tile t = tile_of(P, bid);
+    stagger_loads(P);
 
     const int grp = threadIdx.x / L, j = threadIdx.x % L;
     const bool active = grp < t.nvb;
@@ -341,7 +342,15 @@ static hipError_t launch_bwd_u(const Params &p, int threads, size_t lds, hipStre
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(p.nblocks), dim3(threads), lds, s, p);
+    Params q = p;
+    if (q.stagger > 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(fn), threads, lds);
+        if (e != hipSuccess) return e;
+        q.stagger_cap = per_cu * device_cu_count();
+    }
+    hipLaunchKernelGGL(fn, dim3(q.nblocks), dim3(threads), lds, s, q);
     return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@ __global__ __launch_bounds__(512) void k_forward(Params P)
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem sm = carve(smem, P, blockDim.x / L, false);
     const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    stagger_loads(P);
     forward_tile<L, NPL, F16, BOX, UC>(P, sm, tile_of(P, bid));
 }
 
@@ -56,7 +57,15 @@ static hipError_t launch_fwd_u(const Params &p, int threads, size_t lds, hipStre
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(fn, dim3(p.nblocks), dim3(threads), lds, s, p);
+    Params q = p;
+    if (q.stagger > 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(fn), threads, lds);
+        if (e != hipSuccess) return e;
+        q.stagger_cap = per_cu * device_cu_count();
+    }
+    hipLaunchKernelGGL(fn, dim3(q.nblocks), dim3(threads), lds, s, q);
     return hipGetLastError();
 }
 

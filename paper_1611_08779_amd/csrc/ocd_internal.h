@@ -20,6 +20,8 @@ struct Params {
     int vec_ok;      // vector loads allowed (B even, 16-byte aligned bases)
     int nblocks;
     int reg_uc;      // channel-in-registers plans: compile-time bound on U (else 0)
+    int stagger;     // staged loads: sleep units per 128 workgroups (see stagger_loads)
+    int stagger_cap; // workgroups resident at once: later ones start late anyway
     float Es, N0, beta;
     float lam_default;   // regulariser when lambda == nullptr
     float sqEs;          // sqrt(Es)
@@ -99,6 +101,9 @@ inline size_t mmse_lds_bytes(const Params &p)
     b += (size_t)p.maxslots * p.U * 4;
     return b;
 }
+
+// Compute units of the current device (cached per device; 0 on error).
+int device_cu_count();
 
 // Launchers (one per template instantiation, selected at run time).
 hipError_t launch_forward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,

@@ -1,11 +1,16 @@
 // ocd_jobs.hip -- uneven detection jobs in one persistent launch.
 //
 // Every job is cut into tiles of consecutive (subcarrier, symbol) vectors.  A
-// tile runs exactly the one-problem code (forward_tile) with NPL = 8 complex
-// entries per lane, so a job with B antennas uses L = B/8 lanes per vector
-// (4, 8, 16 or 32): one register footprint serves every job, and a tile of
-// whole subcarriers fills most of a 512-lane workgroup whatever B is, while its
-// H_w slots stay within one LDS budget (two tiles per CU).  Tiles are sorted
+// tile runs exactly the one-problem code (forward_tile).  The lanes per vector
+// follow from the complex entries each lane holds (NPL): a job with B antennas
+// uses L = B / NPL lanes (4, 8, 16 or 32).  The batch tuner picks one of three
+// lane modes for the whole batch: NPL = 8 for every job; NPL = 16 for jobs with
+// B >= 256 (half the lanes per vector: no reduction across DPP rows) and 8 for
+// the others; or in addition NPL = 4 for jobs with B <= 128 (more, shorter lane
+// groups).  Exactly 8 users (16 with 4 entries per lane) take the unrolled user
+// loop.  A tile of whole
+// subcarriers fills most of a 512-lane workgroup whatever B is, while its H_w
+// slots stay within one LDS budget (two tiles per CU).  Tiles are sorted
 // longest-first (LPT) and persistent workgroups pop them from a device counter
 // until the queue is empty.  The queue reset and the persistent kernel can be
 // captured once into a hipGraph and replayed; the job and tile tables live in
@@ -27,14 +32,25 @@
 
 namespace ocd {
 
-constexpr int JOB_NPL = 8;
 constexpr int JOB_THREADS = 512;
 
 struct JobDesc {
     Params P;
     int L;
-    int pad_[3];
+    int npl;   // complex entries per lane
+    int pad_[2];
 };
+
+// Lane modes of the batch tuner: the complex entries per lane for a job with B
+// antennas (the lanes per vector are then B / NPL, rounded up to a power of two).
+constexpr int N_LANE_MODES = 3;
+
+static int lane_mode_npl(int mode, int B)
+{
+    if (mode >= 1 && B > 128) return 16;
+    if (mode == 2 && B > 32) return 4;
+    return 8;
+}
 
 struct TileDesc {
     int vbase;
@@ -52,10 +68,10 @@ constexpr size_t HEADER_BYTES = 256;
 //   persistent = 1: a fixed grid; each workgroup claims its next tile from the
 //                   queue head while it works on the current one.  Every
 //                   workgroup stops when the queue is exhausted.
-template <int L, int UC, bool F16, bool BOX>
+template <int L, int NPL, int UC, bool F16, bool BOX>
 __device__ __forceinline__ void job_tile(const Params &P, unsigned char *smem, const Tile &t)
 {
-    forward_tile<L, JOB_NPL, F16, BOX, UC, false>(P, carve(smem, P, JOB_THREADS / L, false), t);
+    forward_tile<L, NPL, F16, BOX, UC, false>(P, carve(smem, P, JOB_THREADS / L, false), t);
 }
 
 template <bool F16, bool BOX>
@@ -87,18 +103,29 @@ __global__ __launch_bounds__(JOB_THREADS, 4) void k_jobs(const JobDesc *__restri
         t.nvb = __builtin_amdgcn_readfirstlane(td.nvb);
         t.w_first = t.vbase / P.S;
         t.nslots = (t.vbase + t.nvb - 1) / P.S - t.w_first + 1;
-        // 8 users unrolled as in the one-problem kernel (16 would not fit the
-        // register budget of four 512-thread workgroups per CU)
-        const int uc = P.U == 8 ? 8 : 0;
-        switch (jd.L * 100 + uc) {
-        case 400: job_tile<4, 0, F16, BOX>(P, smem, t); break;
-        case 408: job_tile<4, 8, F16, BOX>(P, smem, t); break;
-        case 800: job_tile<8, 0, F16, BOX>(P, smem, t); break;
-        case 808: job_tile<8, 8, F16, BOX>(P, smem, t); break;
-        case 1600: job_tile<16, 0, F16, BOX>(P, smem, t); break;
-        case 1608: job_tile<16, 8, F16, BOX>(P, smem, t); break;
-        case 3208: job_tile<32, 8, F16, BOX>(P, smem, t); break;
-        default: job_tile<32, 0, F16, BOX>(P, smem, t); break;
+        // the unrolled user loop for U = 8 (and U = 16 with 4 entries per lane: with 8,
+        // its registers would not fit the budget of four 512-thread workgroups per CU);
+        // plan_jobs builds only the (L, NPL) pairs below (job_shape_built)
+        const int npl = jd.npl;
+        const int uc = (P.U == 8 && npl <= 8) || (P.U == 16 && npl == 4) ? P.U : 0;
+        switch (jd.L * 10000 + npl * 100 + uc) {
+        case 40800: job_tile<4, 8, 0, F16, BOX>(P, smem, t); break;
+        case 40808: job_tile<4, 8, 8, F16, BOX>(P, smem, t); break;
+        case 80800: job_tile<8, 8, 0, F16, BOX>(P, smem, t); break;
+        case 80808: job_tile<8, 8, 8, F16, BOX>(P, smem, t); break;
+        case 160800: job_tile<16, 8, 0, F16, BOX>(P, smem, t); break;
+        case 160808: job_tile<16, 8, 8, F16, BOX>(P, smem, t); break;
+        case 320800: job_tile<32, 8, 0, F16, BOX>(P, smem, t); break;
+        case 320808: job_tile<32, 8, 8, F16, BOX>(P, smem, t); break;
+        case 160400: job_tile<16, 4, 0, F16, BOX>(P, smem, t); break;
+        case 160408: job_tile<16, 4, 8, F16, BOX>(P, smem, t); break;
+        case 160416: job_tile<16, 4, 16, F16, BOX>(P, smem, t); break;
+        case 320400: job_tile<32, 4, 0, F16, BOX>(P, smem, t); break;
+        case 320408: job_tile<32, 4, 8, F16, BOX>(P, smem, t); break;
+        case 320416: job_tile<32, 4, 16, F16, BOX>(P, smem, t); break;
+        case 161600: job_tile<16, 16, 0, F16, BOX>(P, smem, t); break;
+        case 321600: job_tile<32, 16, 0, F16, BOX>(P, smem, t); break;
+        default: break;   // not built: plan_jobs never produces such a job
         }
         if (!persistent) break;
         __syncthreads();   // this tile is done with LDS (and with s_tile)
@@ -139,7 +166,15 @@ static int tile_vectors(int policy, int L, int S)
     return cap;
 }
 
-static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, JobsPlan &out)
+// The (L, NPL) pairs k_jobs is built for (NPL = 4 and 16 only with a run-time U).
+static bool job_shape_built(int L, int npl)
+{
+    if (npl == 8) return L == 4 || L == 8 || L == 16 || L == 32;
+    return (npl == 16 || npl == 4) && (L == 16 || L == 32);
+}
+
+static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, int lane_mode,
+                            JobsPlan &out)
 {
     out = JobsPlan();
     if (n < 1 || !jobs) return OCD_EINVAL;
@@ -151,9 +186,15 @@ static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, JobsPlan
         if (st != OCD_OK) return st;
         if ((pb->storage == OCD_STORE_F16) != out.f16) return OCD_EINVAL;
         if ((pb->mode != OCD_MMSE) != out.box) return OCD_EINVAL;
-        if (pb->B > JOB_NPL * 32) return OCD_EUNSUPPORTED;
+        if (pb->B > 8 * 32) return OCD_EUNSUPPORTED;
+        int npl_t = lane_mode_npl(lane_mode, pb->B);
         int L = 4;
-        while (JOB_NPL * L < pb->B) L *= 2;
+        while (npl_t * L < pb->B) L *= 2;
+        if (!job_shape_built(L, npl_t)) {   // this job keeps 8 entries per lane
+            npl_t = 8;
+            L = 4;
+            while (npl_t * L < pb->B) L *= 2;
+        }
         ocd_plan pl = {L, tile_vectors(policy, L, pb->S), 0, 0};
         Params P;
         int npl, threads;
@@ -162,7 +203,7 @@ static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, JobsPlan
         // keep two tiles per CU: at most half of the LDS (whole subcarriers first)
         const size_t budget = (size_t)lds_limit_bytes() / 2 - 64;
         while (pl.vectors_per_block >= 1) {
-            if (make_params(pb, pl, nullptr, false, P, npl, threads, lds) && npl == JOB_NPL &&
+            if (make_params(pb, pl, nullptr, false, P, npl, threads, lds) && npl == npl_t &&
                 lds_bytes(P, JOB_THREADS / L, false) <= budget) {
                 lds = lds_bytes(P, JOB_THREADS / L, false);
                 ok = true;
@@ -176,11 +217,12 @@ static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, JobsPlan
         std::memset(&jd, 0, sizeof jd);
         jd.P = P;
         jd.L = L;
+        jd.npl = npl_t;
         out.jobs.push_back(jd);
         out.lds_max = std::max(out.lds_max, lds);
     }
-    char pk[16];
-    std::snprintf(pk, sizeof pk, "|p%d", policy);
+    char pk[32];
+    std::snprintf(pk, sizeof pk, "|p%d|m%d", policy, lane_mode);
     const std::string key = jobs_hash(jobs, n) + pk;
     std::lock_guard<std::mutex> lk(g_tiles_mu);
     auto it = g_tiles.find(key);
@@ -241,11 +283,17 @@ static std::map<std::string, GraphEntry> g_graphs;
 static std::map<std::string, int> g_choice;
 static hipStream_t g_capture_stream = nullptr;
 
-// A schedule choice: persistent (1) or one workgroup per tile (0), times a tile policy.
-constexpr int N_CHOICES = 2 * N_POLICIES;
-constexpr int DEFAULT_CHOICE = 1;   // one workgroup per tile, whole-subcarrier tiles
-static int choice_persistent(int c) { return c / N_POLICIES; }
+// A schedule choice: persistent (1) or one workgroup per tile (0), times a tile
+// policy, times a lane mode.
+constexpr int N_CHOICES = 2 * N_POLICIES * N_LANE_MODES;
+constexpr int DEFAULT_CHOICE = 1;   // one workgroup per tile, whole-subcarrier tiles, NPL 8
+static int choice_lane_mode(int c) { return c / (2 * N_POLICIES); }
+static int choice_persistent(int c) { return (c / N_POLICIES) % 2; }
 static int choice_policy(int c) { return c % N_POLICIES; }
+static int make_choice(int lane_mode, int persistent, int policy)
+{
+    return (lane_mode * 2 + persistent) * N_POLICIES + policy;
+}
 
 // Persistent grid: as many workgroups as fit on the device at once (LDS and the
 // 4-waves-per-SIMD register budget of k_jobs), never more than there are tiles.
@@ -364,7 +412,7 @@ static ocd_status run_choice(const ocd_problem *jobs, int n, int choice, const v
                              unsigned char *ws, size_t ws_bytes, bool use_graph, hipStream_t s)
 {
     JobsPlan jp;
-    ocd_status st = plan_jobs(jobs, n, choice_policy(choice), jp);
+    ocd_status st = plan_jobs(jobs, n, choice_policy(choice), choice_lane_mode(choice), jp);
     if (st != OCD_OK) return st;
     if (HEADER_BYTES + table_bytes(jp) > ws_bytes) return OCD_EINVAL;
     if (jp.tiles->empty()) return OCD_OK;
@@ -410,11 +458,12 @@ using namespace ocd;
 extern "C" size_t ocd_jobs_workspace_bytes(const ocd_problem *jobs, int n_jobs)
 {
     size_t best = 0;
-    for (int policy = 0; policy < N_POLICIES; ++policy) {
-        JobsPlan jp;
-        if (plan_jobs(jobs, n_jobs, policy, jp) != OCD_OK) return 0;
-        best = std::max(best, HEADER_BYTES + table_bytes(jp));
-    }
+    for (int policy = 0; policy < N_POLICIES; ++policy)
+        for (int mode = 0; mode < N_LANE_MODES; ++mode) {
+            JobsPlan jp;
+            if (plan_jobs(jobs, n_jobs, policy, mode, jp) != OCD_OK) return 0;
+            best = std::max(best, HEADER_BYTES + table_bytes(jp));
+        }
     return best;
 }
 
@@ -460,9 +509,32 @@ extern "C" ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const
         choice = best;
         g_choice[hk] = choice;
     }
-    if (flags & OCD_JOBS_PERSISTENT) choice = N_POLICIES + choice_policy(choice);
+    if (flags & OCD_JOBS_PERSISTENT)
+        choice = make_choice(choice_lane_mode(choice), 1, choice_policy(choice));
+    const int forced_mode = (flags >> OCD_JOBS_LANE_MODE_SHIFT) & 3;
+    if (forced_mode > N_LANE_MODES) return OCD_EINVAL;
+    if (forced_mode)
+        choice = make_choice(forced_mode - 1, choice_persistent(choice), choice_policy(choice));
     return run_choice(jobs, n_jobs, choice, H, y, z, llr, ws, workspace_bytes,
                       (flags & OCD_JOBS_GRAPH) != 0, stream);
+}
+
+extern "C" ocd_status ocd_jobs_schedule(const ocd_problem *jobs, int n_jobs, int *persistent,
+                                        int *tile_policy, int *lane_mode)
+{
+    if (!jobs || n_jobs < 1 || !persistent || !tile_policy || !lane_mode) return OCD_EINVAL;
+    for (int j = 0; j < n_jobs; ++j) {
+        ocd_status st = validate(&jobs[j]);
+        if (st != OCD_OK) return st;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    int choice = DEFAULT_CHOICE;
+    auto it = g_choice.find(jobs_hash(jobs, n_jobs));
+    if (it != g_choice.end()) choice = it->second;
+    *persistent = choice_persistent(choice);
+    *tile_policy = choice_policy(choice);
+    *lane_mode = choice_lane_mode(choice);
+    return OCD_OK;
 }
 
 extern "C" void ocd_release_graphs(void)

@@ -65,6 +65,20 @@ __device__ __forceinline__ int slot_of_group(const Params &P, const Tile &tile, 
     return (int)divide_invariant((unsigned)x, P.divS_m, P.divS_s1, P.divS_s2);
 }
 
+// Staggered staging: workgroups are dispatched in blockIdx order, so the ones
+// launched first sit on every CU before later ones arrive.  If all of them issue
+// their loads at once, HBM serves the requests interleaved and every workgroup
+// gets its data late; delaying workgroup b by max(0, b/128 - 1) * stagger units of
+// 512 clocks lets the first ones (the first 256 unchanged) start computing while
+// later ones load.  Workgroups beyond the first stagger_cap (those resident at
+// once) are dispatched only as earlier ones retire and do not wait.
+__device__ __forceinline__ void stagger_loads(const Params &P)
+{
+    if (P.stagger <= 0 || (int)blockIdx.x >= P.stagger_cap) return;
+    const int n = ((int)blockIdx.x / 128 - 1) * P.stagger;
+    for (int i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(8);   // 8 x 64 clocks
+}
+
 __device__ __forceinline__ Tile tile_of(const Params &P, int bid)
 {
     Tile t;
@@ -433,7 +447,9 @@ __device__ __forceinline__ void axpy_add(const float2 *h, float2 a, float2 *r)
 // One coordinate update of Algorithm 1 for the lanes of a group:
 //   z_u' = proj(d_u^-1 h_u^H r + p_u z_u),  r <- r - h_u (z_u' - z_u).
 // h: this lane's part of column u; dp = (d_u^-1, p_u); zo = z_u.  Returns z_u'.
-template <int L, int NPL, bool BOX, int CHAINS = 1, typename HT>
+// UPDATE_R = false leaves r as it is: the last update of the last sweep, after
+// which the residual is never read again.
+template <int L, int NPL, bool BOX, int CHAINS = 1, bool UPDATE_R = true, typename HT>
 __device__ __forceinline__ float2 coordinate_update(const HT *h, float2 dp, float2 zo,
                                                     float beta, float2 *r)
 {
@@ -449,6 +465,7 @@ __device__ __forceinline__ float2 coordinate_update(const HT *h, float2 dp, floa
     // negated copy would cost one instruction per entry).  Im Delta = -ndi enters as a
     // negated operand, which the FMA takes for free (a - b is exactly -(b - a)).
     // Same bits as axpy_sub.
+    if constexpr (!UPDATE_R) return make_float2(cr, ci);
     const float ndr = zo.x - cr, ndi = zo.y - ci;
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {

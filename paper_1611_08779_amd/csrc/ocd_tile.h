@@ -75,7 +75,10 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
             for (int u = 0; u < UC; ++u) {
                 float2 h[NPL];
                 load_column<L, NPL>(Hs + u * BP, j, h);
-                zr[u] = coordinate_update<L, NPL, BOX>(h, dpk[u], zr[u], beta, r);
+                if (u == UC - 1 && k == P.K - 1)   // r is not read after the last update
+                    zr[u] = coordinate_update<L, NPL, BOX, 1, false>(h, dpk[u], zr[u], beta, r);
+                else
+                    zr[u] = coordinate_update<L, NPL, BOX>(h, dpk[u], zr[u], beta, r);
             }
             if (P.z_hist) {
 #pragma unroll

@@ -161,11 +161,15 @@ def test_jobs_rejects_null_arguments(lib):
 
 class Plan(ctypes.Structure):
     _fields_ = [("lanes_per_vector", ctypes.c_int), ("vectors_per_block", ctypes.c_int),
-                ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int)]
+                ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int),
+                ("stagger", ctypes.c_int)]
 
 
 REG_PLANS = [
     # (problem overrides, plan, expected status)
+    (dict(), (16, 14, 1, 0, 2), 0),          # staggered staging
+    (dict(), (16, 14, 1, 0, 17), -2),        # stagger beyond 16
+    (dict(), (16, 14, 1, 0, -1), -2),
     (dict(S=1), (16, 16, 0, 1), 0),
     (dict(S=1), (32, 8, 0, 1), 0),
     (dict(S=1), (32, 9, 0, 1), -2),          # more than 256 lanes per workgroup

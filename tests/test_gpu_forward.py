@@ -37,7 +37,7 @@ def run_and_compare(ocd, B, U, W, S, Q, K, mode, snr, seed, lam=None, beta=0.0, 
     lam_t = None if lam is None else dev(np.asarray(lam, np.float32))
     if plan is not None:
         pb = ocd.problem(B, U, W, S, Q, K, mode, "f32", N0, Es, beta)
-        ocd.ocd_set_plan(pb, ocd.Plan(*(tuple(plan) + (0,) * (4 - len(plan)))))
+        ocd.ocd_set_plan(pb, ocd.Plan(*(tuple(plan) + (0,) * (5 - len(plan)))))
     z, L, zh = ocd.detect(dev(wl["H"]), dev(wl["y"]), K, Q, mode, N0, Es, beta, lam=lam_t,
                           want_hist=hist)
     torch.cuda.synchronize()
@@ -90,7 +90,7 @@ def _full_slot_against_oracle(ocd, pb, wl, want_plan=None):
     say("  plan used %s" % used.as_dict())
     if want_plan is not None:
         assert (used.lanes_per_vector, used.vectors_per_block, used.xcd_remap,
-                used.channel_in_registers) == want_plan
+                used.channel_in_registers, used.stagger) == want_plan
     z, L, _ = ocd.detect(H, y, 3, 6, "mmse", N0)
     torch.cuda.synchronize()
     zo, Lo, _ = oracle_ref(wl["H"], wl["y"], 3, 6, "mmse", N0)
@@ -101,18 +101,20 @@ def _full_slot_against_oracle(ocd, pb, wl, want_plan=None):
     return used
 
 
-def test_b128_u8_64qam_full_slot_bench_plan_forced(ocd):
-    """The headline slot whole (16,800 vectors) under the launch plan the benchmark's
+@pytest.mark.parametrize("stagger", [0, 2])
+def test_b128_u8_64qam_full_slot_bench_plan_forced(ocd, stagger):
+    """The headline slot whole (16,800 vectors) under the launch plans the benchmark's
     autotuner picks on MI355X: 16 lanes per vector (8 complex entries per lane), one
     subcarrier's 14 symbols per workgroup (the dense one-subcarrier staging path),
-    XCD-aware tile order; U = 8 takes the unrolled user loop.  That is the kernel
-    instance k_forward<L=16, NPL=8, FP32, MMSE, U=8>, checked against the oracle."""
+    XCD-aware tile order, with and without staggered staging; U = 8 takes the
+    unrolled user loop.  That is the kernel instance k_forward<L=16, NPL=8, FP32,
+    MMSE, U=8>, checked against the oracle."""
     B, U, W, S, Q, K = 128, 8, 1200, 14, 6, 3
-    say("case headline slot, bench plan (16, 14, 1, 0)")
+    say("case headline slot, bench plan (16, 14, 1, 0, %d)" % stagger)
     wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[2, 0, 1])
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", f32(wl["N0"]))
-    ocd.ocd_set_plan(pb, ocd.Plan(16, 14, 1, 0))
-    _full_slot_against_oracle(ocd, pb, wl, want_plan=(16, 14, 1, 0))
+    ocd.ocd_set_plan(pb, ocd.Plan(16, 14, 1, 0, stagger))
+    _full_slot_against_oracle(ocd, pb, wl, want_plan=(16, 14, 1, 0, stagger))
 
 
 def test_b128_u8_64qam_full_slot_bench_autotuned(ocd):
@@ -131,7 +133,7 @@ def test_b128_u8_64qam_full_slot_bench_autotuned(ocd):
     say("  autotuned %s" % tuned.as_dict())
     _full_slot_against_oracle(ocd, pb, wl, want_plan=(
         tuned.lanes_per_vector, tuned.vectors_per_block, tuned.xcd_remap,
-        tuned.channel_in_registers))
+        tuned.channel_in_registers, tuned.stagger))
 
 
 @pytest.mark.parametrize("plan", [(16, 4, 0, 1), (32, 4, 0, 1)])
@@ -143,7 +145,8 @@ def test_b128_u8_64qam_one_h_per_vector_full_size(ocd, plan):
 
 
 @pytest.mark.parametrize("plan", [(4, 14, 0), (4, 16, 1), (8, 28, 0), (8, 64, 1), (16, 32, 0),
-                                  (16, 14, 1), (16, 14, 0), (16, 28, 1)])
+                                  (16, 14, 1), (16, 14, 0), (16, 28, 1), (16, 14, 1, 0, 4),
+                                  (8, 28, 0, 0, 1), (16, 16, 1, 0, 2)])
 def test_b128_u8_64qam_slice_plans(ocd, plan):
     run_and_compare(ocd, 128, 8, 60, 14, 6, 3, "mmse", 20.0, [2, 1, 0], plan=plan)
 

@@ -71,6 +71,53 @@ def test_jobs_match_oracle_and_single_launches(ocd):
         assert torch.equal(z1, z[j]) and torch.equal(L1, L[j]), j
 
 
+def _lanes_npl(B, mode):
+    # lane modes of the batched kernel: entries per lane by B, lanes per vector B / NPL
+    npl = 16 if (mode >= 1 and B > 128) else 4 if (mode == 2 and B > 32) else 8
+    L = 4
+    while npl * L < B:
+        L *= 2
+    if not ((npl == 8 and L in (4, 8, 16, 32)) or (npl in (4, 16) and L in (16, 32))):
+        npl, L = 8, _lanes(B)
+    return L, npl
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("persistent", [False, True])
+def test_jobs_every_lane_mode(ocd, mode, persistent):
+    """Each lane mode of the batched kernel (8 entries per lane; 16 for B > 128; and 4
+    for 32 < B <= 128), forced through the flags, in both schedules: every job against
+    the oracle, and bit for bit against a one-problem launch with the same lanes per
+    vector (the one-problem kernel unrolls U = 8 and 16 where the batched one may run the
+    loop over a run-time U: the same arithmetic in the same order)."""
+    probs, Hs, ys, wls = _make(ocd)
+    flags = ocd.OCD_JOBS_LANE_MODE(mode) | (ocd.OCD_JOBS_PERSISTENT if persistent else 0)
+    say("jobs: lane mode %d persistent %s" % (mode, persistent))
+    z, L, ws = ocd.detect_jobs(probs, Hs, ys, flags=flags)
+    torch.cuda.synchronize()
+    for j, (pb, wl) in enumerate(zip(probs, wls)):
+        zo, Lo, _ = oracle_ref(wl["H"], wl["y"], pb.K, pb.Q, "mmse", pb.N0)
+        assert z_rel_err(host(z[j]), zo) <= Z_TOL_F32, j
+        assert llr_rel_err(host(L[j]), Lo) <= LLR_TOL_F32, j
+        lanes, npl = _lanes_npl(pb.B, mode)
+        ocd.ocd_set_plan(pb, ocd.Plan(lanes, 14, 0, 0))
+        z1, L1, _ = ocd.detect(Hs[j], ys[j], pb.K, pb.Q, "mmse", pb.N0)
+        torch.cuda.synchronize()
+        assert torch.equal(z1, z[j]) and torch.equal(L1, L[j]), (j, lanes, npl)
+
+
+def test_jobs_schedule_reports_the_tuned_choice(ocd):
+    probs, Hs, ys, wls = _make(ocd, jobs=JOBS[:4])
+    before = ocd.ocd_jobs_schedule(probs)
+    z, L, ws = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_TUNE)
+    torch.cuda.synchronize()
+    after = ocd.ocd_jobs_schedule(probs)
+    say("jobs schedule default %s tuned %s" % (before, after))
+    assert before == {"persistent": 0, "tile_policy": 1, "lane_mode": 0} or before == after
+    assert after["persistent"] in (0, 1) and after["tile_policy"] in (0, 1, 2)
+    assert after["lane_mode"] in (0, 1, 2)
+
+
 def test_jobs_persistent_schedule_matches(ocd):
     """The persistent schedule (workgroups popping tiles from the device queue)
     computes the same bits as one workgroup per tile."""
