@@ -852,20 +852,43 @@ def fwd_bwd_form(torch, np, ocd, synth, dev):
     torch.cuda.synchronize()
     agree = all(float((a - b).abs().max()) <= 1e-4 * max(float(b.abs().max()), 1e-30)
                 for a, b in zip((dlam, dbeta, dy), ref))
+    loss1 = torch.empty(1, device=dev)
+
+    def train_step():
+        # one launch: forward, loss, loss gradient and the reverse sweeps
+        ocd.ocd_detect_train_bce(pb5, wl["H"], wl["y"], lam, bits_u8, None, None, loss1, dlam,
+                                 dbeta, dy, wsb)
+
+    ref = [t.clone() for t in (dlam, dbeta, dy)]
+    loss_ref = float(torch.nn.functional.binary_cross_entropy_with_logits(L5.double(),
+                                                                          bits.double()))
+    train_step()
+    torch.cuda.synchronize()
+    train_agree = all(float((a - b).abs().max()) <= 1e-4 * max(float(b.abs().max()), 1e-30)
+                      for a, b in zip((dlam, dbeta, dy), ref))
+    train_agree = train_agree and abs(float(loss1) - loss_ref) <= 1e-5 * loss_ref
+    plan_t = ocd.ocd_train_plan(pb5)
+    tts, _ = time_graph(torch, GraphedSteps(torch, [train_step] * 8), 400, 16)
     tfb, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd_fused] * 8), 400, 16)
     tfb2, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd] * 8), 400, 16)
     tf, _ = time_graph(torch, GraphedSteps(torch, [fwd_only] * 8), 400, 16)
     fl, _ = algorithmic(B5, U5, S5, K5, Q5)
     return {
-        "vectors_per_s": W5 * S5 / tfb, "ms_per_step": tfb * 1e3,
-        "loss_gradient": "formed in the adjoint kernel from the bits (ocd_detect_backward_bce)",
-        "two_step_vectors_per_s": W5 * S5 / tfb2,
+        "vectors_per_s": W5 * S5 / tts, "ms_per_step": tts * 1e3,
+        "step": "one launch of ocd_detect_train_bce: detection, mean BCE of the LLRs, "
+                "dLoss/dlambda_k, dLoss/dbeta, dLoss/dy",
+        "train_step_matches_two_launch": bool(train_agree),
+        "two_launch_vectors_per_s": W5 * S5 / tfb,
+        "two_launch_loss_gradient": "formed in the adjoint kernel from the bits "
+                                    "(ocd_detect + ocd_detect_backward_bce)",
+        "three_step_vectors_per_s": W5 * S5 / tfb2,
         "fused_matches_two_step": bool(agree),
-        "fwd_vectors_per_s": W5 * S5 / tf, "bwd_over_fwd_time": (tfb - tf) / tf,
+        "fwd_vectors_per_s": W5 * S5 / tf, "step_over_fwd_time": tts / tf,
         "workload": "B=128 U=16, 2048 subcarriers x 4 symbols, 16-QAM, K=4, HYBRID (learnable "
                     "lambda_k, beta), BCE of LLRs, 10 dB",
         "fwd_tflops": fl * W5 * S5 / tf / 1e12,
         "plan_forward": plan_f.as_dict(), "plan_backward": plan_b.as_dict(),
+        "plan_train": plan_t.as_dict(),
     }
 
 

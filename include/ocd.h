@@ -114,8 +114,9 @@ ocd_status ocd_detect(const ocd_problem *pb, const void *H, const void *y, const
                       const float *g, const float *dinv, const float *p,
                       float *z, float *llr, float *z_hist, hipStream_t stream);
 
-/* Bytes of device workspace ocd_detect_backward needs for this problem: 256 bytes
- * holding a completion counter, then K + 1 partial sums per workgroup. */
+/* Bytes of device workspace ocd_detect_backward and ocd_detect_train_bce need for
+ * this problem: 256 bytes holding a completion counter, then up to K + 2 partial sums
+ * per workgroup. */
 size_t ocd_backward_workspace_bytes(const ocd_problem *pb);
 
 /* Adjoint of ocd_detect with respect to the per-sweep regularisers, the box
@@ -163,6 +164,29 @@ ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void *H, const v
                                    const float *lambda, const float *z_hist, const uint8_t *bits,
                                    float *dlambda, float *dbeta, float *dy,
                                    void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* One training step of the unfolded detector in one launch: Algorithm 1 and the
+ * soft output of Section III-C (as ocd_detect), the mean binary cross-entropy of the
+ * LLRs against the transmitted bits (as ocd_detect_backward_bce),
+ *   loss = mean over the W S U Q bits of softplus(L) - bit L   (P(bit = 1) = sigmoid(L)),
+ * and its gradients with respect to the per-sweep regularisers, the box half-width
+ * and the receive vectors.  Each workgroup stages its channels once for both passes
+ * and keeps every vector's z after each sweep in LDS, so no per-sweep history
+ * crosses HBM.  z, the LLRs and dy are those of ocd_detect followed by
+ * ocd_detect_backward_bce under the same plan, bit for bit; the loss is summed in a
+ * fixed order (repeated calls give identical bits).
+ *   bits        device uint8 [W][S][U][Q], 0 or 1, in the LLR layout
+ *   z, llr      outputs as in ocd_detect, each may be NULL (not written)
+ *   loss        device [1], the mean cross-entropy (overwritten; 0 when W = 0)
+ *   dlambda, dbeta, dy, workspace   as in ocd_detect_backward (dy may be NULL)
+ * The plan is the adjoint's (ocd_autotune_backward's cached one, else the heuristic
+ * one) with its vectors per workgroup halved until the z history fits in LDS; see
+ * ocd_train_plan.  Returns OCD_EINVAL for a NULL loss, dlambda or dbeta, for NULL H, y
+ * or bits when W > 0, and for a workspace that is too small or not 16-byte aligned. */
+ocd_status ocd_detect_train_bce(const ocd_problem *pb, const void *H, const void *y,
+                                const float *lambda, const uint8_t *bits, float *z, float *llr,
+                                float *loss, float *dlambda, float *dbeta, float *dy,
+                                void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Capacity, per GPU, of the static device scratch of ocd_detect_backward_bce_noalloc. */
 #define OCD_NOALLOC_SCRATCH_BYTES (1u << 20)
@@ -220,6 +244,9 @@ typedef struct {
 
 /* The plan ocd_detect would use for this problem (cached or heuristic). */
 ocd_status ocd_get_plan(const ocd_problem *pb, ocd_plan *plan);
+
+/* The launch plan ocd_detect_train_bce takes for this shape (see there). */
+ocd_status ocd_train_plan(const ocd_problem *pb, ocd_plan *plan);
 
 /* Force a plan for this problem's shape (B, U, W, S, K, Q, mode, storage), with and
  * without per-sweep regularisers (the backward pass keeps its own choice). */

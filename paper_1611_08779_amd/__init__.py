@@ -31,11 +31,12 @@ __all__ = [
     "Problem", "Plan", "OCDError", "MODES", "STORAGES", "LIB_PATH",
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_detect_backward_bce",
+    "ocd_detect_backward_bce_noalloc", "ocd_detect_train_bce", "ocd_train_plan",
     "ocd_get_plan", "ocd_set_plan",
     "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
     "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed", "ocd_ofdm_demodulate",
     "OfdmShape", "ofdm_demodulate",
-    "problem", "detect", "preprocess", "backward", "detect_jobs", "detect_mmse", "detect_fixed",
+    "problem", "detect", "preprocess", "backward", "train_step", "detect_jobs", "detect_mmse", "detect_fixed",
     "OCD_JOBS_GRAPH",
     "OCD_JOBS_TUNE",
     "OCD_JOBS_PERSISTENT", "OCD_JOBS_LANE_MODE", "JobsCall", "ocd_jobs_schedule",
@@ -116,6 +117,9 @@ def _load():
         "ocd_detect_backward": ([P, vp, vp, fp, fp, fp, fp, fp, fp, vp, sz, vp], ctypes.c_int),
         "ocd_detect_backward_bce": ([P, vp, vp, fp, fp, vp, fp, fp, fp, vp, sz, vp], ctypes.c_int),
         "ocd_detect_backward_bce_noalloc": ([P, vp, vp, fp, fp, vp, fp, fp, fp, vp], ctypes.c_int),
+        "ocd_detect_train_bce": ([P, vp, vp, fp, vp, fp, fp, fp, fp, fp, fp, vp, sz, vp],
+                                 ctypes.c_int),
+        "ocd_train_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_get_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_set_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_autotune": ([P, vp, vp, fp, fp, ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
@@ -293,6 +297,35 @@ def ocd_detect_backward_bce_noalloc(pb: Problem, H, y, lam, z_hist, bits, dlam, 
         _dev_ptr(dbeta, "dbeta", f32, 4, dev),
         _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev), _stream(stream))
     _check("ocd_detect_backward_bce_noalloc", st)
+
+
+def ocd_detect_train_bce(pb: Problem, H, y, lam, bits, z, llr, loss, dlam, dbeta, dy, workspace,
+                         stream=None) -> None:
+    """One training step in one launch: detection, the mean BCE of the LLRs against
+    bits (uint8 [W,S,U,Q]) into loss [1], and its gradients dlam, dbeta, dy."""
+    dev = H.device
+    f32 = (torch.float32,)
+    zt = (torch.complex64, torch.float32)
+    ws_need = ocd_backward_workspace_bytes(pb)
+    st = _lib.ocd_detect_train_bce(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(bits, "bits", (torch.uint8,), pb.W * pb.S * pb.U * pb.Q, dev),
+        _dev_ptr(z, "z", zt, pb.W * pb.S * pb.U * 8, dev),
+        _dev_ptr(llr, "llr", f32, pb.W * pb.S * pb.U * pb.Q * 4, dev),
+        _dev_ptr(loss, "loss", f32, 4, dev),
+        _dev_ptr(dlam, "dlam", f32, pb.K * 4, dev),
+        _dev_ptr(dbeta, "dbeta", f32, 4, dev),
+        _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
+        _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, _stream(stream))
+    _check("ocd_detect_train_bce", st)
+
+
+def ocd_train_plan(pb: Problem) -> Plan:
+    pl = Plan()
+    _check("ocd_train_plan", _lib.ocd_train_plan(ctypes.byref(pb), ctypes.byref(pl)))
+    return pl
 
 
 def ocd_get_plan(pb: Problem) -> Plan:
@@ -495,6 +528,27 @@ def backward(H, y, z_hist, dllr, K, Q, mode="mmse", N0=1.0, Es=1.0, beta=0.0, la
     else:
         ocd_detect_backward(pb, H, y, lam, z_hist, dllr, dlam, dbeta, dy, ws, stream)
     return dlam, dbeta, dy
+
+
+def train_step(H, y, bits, K, Q, mode="hybrid", N0=1.0, Es=1.0, beta=0.0, lam=None,
+               storage="f32", want_z=False, want_llr=False, want_dy=True, workspace=None,
+               stream=None):
+    """Runs ocd_detect_train_bce; returns (loss [1], dlam [K], dbeta [1], dy or None,
+    z or None, llr or None)."""
+    W, U, B, S = _shape_of(H, y, storage)
+    pb = problem(B, U, W, S, Q, K, mode, storage, N0, Es, beta)
+    dev = H.device
+    loss = torch.empty(1, device=dev, dtype=torch.float32)
+    dlam = torch.empty(K, device=dev, dtype=torch.float32)
+    dbeta = torch.empty(1, device=dev, dtype=torch.float32)
+    dy = torch.empty(W, S, B, device=dev, dtype=torch.complex64) if want_dy else None
+    z = torch.empty(W, S, U, device=dev, dtype=torch.complex64) if want_z else None
+    llr = torch.empty(W, S, U, Q, device=dev, dtype=torch.float32) if want_llr else None
+    ws = workspace
+    if ws is None:   # the completion counter starts at zero
+        ws = torch.zeros(ocd_backward_workspace_bytes(pb), device=dev, dtype=torch.uint8)
+    ocd_detect_train_bce(pb, H, y, lam, bits, z, llr, loss, dlam, dbeta, dy, ws, stream)
+    return loss, dlam, dbeta, dy, z, llr
 
 
 def detect_mmse(H, y, Q, N0=1.0, Es=1.0, storage="f32", want_z=True, want_llr=True, plan=None,

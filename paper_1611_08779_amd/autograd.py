@@ -2,8 +2,8 @@
 ``ocd_detect`` (forward, keeping the per-sweep history of z) and
 ``ocd_detect_backward`` (the hand-written adjoint kernel), and a second one for
 the training loss itself, the mean binary cross-entropy of the LLRs against the
-transmitted bits, whose backward is ``ocd_detect_backward_bce`` (dLoss/dLLR
-formed inside the adjoint kernel).
+transmitted bits, whose forward is one launch of the training step
+``ocd_detect_train_bce`` (the loss and its gradients together).
 
 Learnable quantities: the per-sweep regularisers ``lam`` ([K], the HYBRID
 mode's lambda_k), the box half-width ``beta`` (a one-element tensor) and the
@@ -15,7 +15,8 @@ from __future__ import annotations
 
 import torch
 
-from . import (backward as _ocd_backward, detect as _ocd_detect, problem as _problem)
+from . import (backward as _ocd_backward, detect as _ocd_detect, problem as _problem,
+               train_step as _train_step)
 
 __all__ = ["OCDFunction", "ocd_llr", "OCDBCEFunction", "ocd_bce_loss"]
 
@@ -55,8 +56,8 @@ def ocd_llr(y, H, K, Q, mode="hybrid", N0=1.0, Es=1.0, lam=None, beta=None, stor
 
 class OCDBCEFunction(torch.autograd.Function):
     """loss = mean over the W S U Q bits of softplus(L) - bit L, L = OCD(y; lam, beta, H):
-    the forward runs ocd_detect and the loss in torch; the backward is one launch of
-    the adjoint with the loss gradient formed from the bits (no dLoss/dLLR array)."""
+    one launch of the training step (ocd_detect_train_bce) computes the loss and its
+    gradients together; the backward only scales them by the upstream gradient."""
 
     @staticmethod
     def forward(ctx, y, lam, beta, H, bits, K, Q, mode, N0, Es, storage):
@@ -64,20 +65,17 @@ class OCDBCEFunction(torch.autograd.Function):
         lam_c = lam.detach().contiguous().float() if lam is not None else None
         y_c = y.detach().contiguous()
         bits_u8 = bits.detach().to(torch.uint8).contiguous()
-        _, llr, z_hist = _ocd_detect(H, y_c, K, Q, mode, N0, Es, beta_val, lam=lam_c,
-                                     storage=storage, want_z=False, want_llr=True, want_hist=True)
-        loss = torch.nn.functional.binary_cross_entropy_with_logits(llr, bits_u8.float())
-        ctx.save_for_backward(y_c, H, z_hist, lam_c, bits_u8)
-        ctx.cfg = (K, Q, mode, N0, Es, beta_val, storage, lam is not None, beta is not None)
-        return loss
+        loss, dlam, dbeta, dy, _, _ = _train_step(H, y_c, bits_u8, K, Q, mode, N0, Es, beta_val,
+                                                  lam=lam_c, storage=storage,
+                                                  want_dy=ctx.needs_input_grad[0])
+        ctx.save_for_backward(dlam, dbeta, dy)
+        ctx.cfg = (lam is not None, beta is not None)
+        return loss.reshape(())
 
     @staticmethod
     def backward(ctx, grad_loss):
-        y, H, z_hist, lam, bits = ctx.saved_tensors
-        K, Q, mode, N0, Es, beta_val, storage, has_lam, has_beta = ctx.cfg
-        dlam, dbeta, dy = _ocd_backward(H, y, z_hist, None, K, Q, mode, N0, Es, beta_val, lam=lam,
-                                        storage=storage, want_dy=ctx.needs_input_grad[0],
-                                        bits=bits)
+        dlam, dbeta, dy = ctx.saved_tensors
+        has_lam, has_beta = ctx.cfg
         gy = dy * grad_loss if ctx.needs_input_grad[0] else None
         glam = dlam * grad_loss if has_lam and ctx.needs_input_grad[1] else None
         gbeta = dbeta * grad_loss if has_beta and ctx.needs_input_grad[2] else None

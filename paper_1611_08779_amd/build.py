@@ -19,7 +19,8 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "ocd")
 LIB = os.path.join(PKG, "libocd.so")
 
-SOURCES = ["ocd_api.hip", "ocd_forward.hip", "ocd_forward_reg.hip", "ocd_backward.hip", "ocd_jobs.hip",
+SOURCES = ["ocd_api.hip", "ocd_forward.hip", "ocd_forward_reg.hip", "ocd_backward.hip", "ocd_train.hip",
+           "ocd_jobs.hip",
            "ocd_mmse.hip", "ocd_fixed.hip", "ocd_ofdm.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

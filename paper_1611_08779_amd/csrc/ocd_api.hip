@@ -612,9 +612,9 @@ extern "C" size_t ocd_backward_workspace_bytes(const ocd_problem *pb)
 {
     if (validate(pb) != OCD_OK) return 0;
     // the completion ticket (256 bytes), then the block partials of
-    // (dlambda_1..K, dbeta) for the plan with the most blocks
+    // (dlambda_1..K, dbeta, loss) for the plan with the most blocks
     const long nvec = (long)pb->W * pb->S;
-    return 256 + (size_t)std::max(1L, nvec) * (size_t)(pb->K + 1) * sizeof(float);
+    return 256 + (size_t)std::max(1L, nvec) * (size_t)(pb->K + 2) * sizeof(float);
 }
 
 namespace ocd {
@@ -664,7 +664,7 @@ static ocd_status run_backward(const ocd_problem *pb, const ocd_plan &pl, const 
                             lds, stream);
     } else {
         P.nblocks = 0;   // no workgroups: zero gradients
-        e = launch_reduce_partials(P, dlambda, dbeta, stream);
+        e = launch_reduce_partials(P, dlambda, dbeta, nullptr, stream);
     }
     return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
 }
@@ -695,6 +695,85 @@ extern "C" ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void 
     if (st != OCD_OK) return st;
     return run_backward(pb, choose_plan(pb, lambda, true), H, y, lambda, z_hist, nullptr, dlambda,
                         dbeta, dy, workspace, stream, bits);
+}
+
+// ------------------------------------------------------------------ training step
+
+namespace ocd {
+
+// A training-step launch takes the adjoint's plan; each vector's K rows of z
+// history join its LDS, so the vectors per workgroup are halved until they fit.
+static bool make_train_params(const ocd_problem *pb, ocd_plan pl, const float *lambda, Params &P,
+                              int &npl, int &threads, size_t &lds, ocd_plan *used)
+{
+    for (;;) {
+        if (make_params(pb, pl, lambda, true, P, npl, threads, lds)) {
+            lds = lds_bytes(P, threads / pl.lanes_per_vector, true, threads / 64, true);
+            if (lds <= (size_t)lds_limit_bytes()) {
+                if (used) *used = pl;
+                return true;
+            }
+        }
+        if (pl.vectors_per_block <= 1) return false;
+        pl.vectors_per_block /= 2;
+    }
+}
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_train_plan(const ocd_problem *pb, ocd_plan *plan)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!plan) return OCD_EINVAL;
+    Params P;
+    int npl, threads;
+    size_t lds;
+    if (!make_train_params(pb, choose_plan(pb, nullptr, true), nullptr, P, npl, threads, lds, plan))
+        return OCD_EUNSUPPORTED;
+    return OCD_OK;
+}
+
+extern "C" ocd_status ocd_detect_train_bce(const ocd_problem *pb, const void *H, const void *y,
+                                           const float *lambda, const uint8_t *bits, float *z,
+                                           float *llr, float *loss, float *dlambda, float *dbeta,
+                                           float *dy, void *workspace, size_t workspace_bytes,
+                                           hipStream_t stream)
+{
+    ocd_status st = validate(pb);
+    if (st != OCD_OK) return st;
+    if (!loss || !dlambda || !dbeta) return OCD_EINVAL;
+    if (pb->W > 0 && (!H || !y || !bits)) return OCD_EINVAL;
+    if (workspace_bytes < ocd_backward_workspace_bytes(pb) || !workspace) return OCD_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace) % 16) return OCD_EINVAL;
+    Params P;
+    int npl, threads;
+    size_t lds;
+    ocd_plan pl;
+    if (!make_train_params(pb, choose_plan(pb, lambda, true), lambda, P, npl, threads, lds, &pl))
+        return OCD_EUNSUPPORTED;
+    P.H = H; P.y = y;
+    P.bits = bits;
+    const double nbits = (double)pb->W * pb->S * pb->U * pb->Q;
+    P.inv_nbits = nbits > 0 ? (float)(1.0 / nbits) : 0.f;
+    P.z = reinterpret_cast<float2 *>(z);
+    P.llr = llr;
+    P.dy = reinterpret_cast<float2 *>(dy);
+    P.ticket = reinterpret_cast<unsigned *>(workspace);
+    P.partials = reinterpret_cast<float *>(static_cast<unsigned char *>(workspace) + 256);
+    P.dlambda = dlambda;
+    P.dbeta = dbeta;
+    P.loss = loss;
+    set_vec_ok(P, pb, H, y);
+    hipError_t e;
+    if (pb->W > 0) {
+        e = launch_train(pl.lanes_per_vector, npl, pb->storage == OCD_STORE_F16, P, threads, lds,
+                         stream);
+    } else {
+        P.nblocks = 0;   // no workgroups: zero gradients and loss
+        e = launch_reduce_partials(P, dlambda, dbeta, loss, stream);
+    }
+    return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
 }
 
 // ------------------------------------------------------------------ adjoint without allocation

@@ -20,147 +20,19 @@
 // The last workgroup to finish (a completion ticket taken with one device-scope
 // atomic from a vector lane) sums them in workgroup order and writes dlambda and
 // dbeta: a fixed order, so the gradients are bitwise reproducible, and no second
-// launch (finish_partials; the partials travel through the caches, not the L2s).  The ticket counts to the number of workgroups and is set back to zero
-// by that last workgroup, so it is zero again after every launch.
-#include "ocd_stage.h"
+// launch (finish_partials in ocd_adjoint.h: the partials travel through the
+// caches, not the L2s).  The ticket counts to the number of workgroups and is set
+// back to zero by that last workgroup, so it is zero again after every launch.
+#include "ocd_adjoint.h"
 
 namespace ocd {
 
-// dLoss/dLLR of the mean binary cross-entropy softplus(L) - bit L over n bits
-// (P(bit = 1) = sigmoid(L)): (sigmoid(L) - bit) / n.
-__device__ __forceinline__ float bce_grad(float L, unsigned char bit, float inv_n)
-{
-    return (1.0f / (1.0f + expf(-L)) - (float)bit) * inv_n;
-}
-
-// dLoss/dz of one user from dLoss/dLLR through L_b = rho * D_b(x), x = z/(mu sqrt(Es)),
-// and the contribution of mu(lambda_K), rho(lambda_K) to dLoss/dlambda_K.  dLoss/dLLR
-// is read from Lbar, or (Lbar null) formed from the user's bits for the mean BCE of
-// the LLRs, L_b recomputed here.
-template <int HALF>
-__device__ __forceinline__ void user_llr_adjoint(const float *Lbar, const unsigned char *bits,
-                                                 float inv_n, float xr, float xi, float s,
-                                                 float mu, float rho, float scale, float2 *zbar,
-                                                 float *dmu, float *drho)
-{
-    float Dr[HALF], Di[HALF];
-    axis_llr<HALF>(xr, scale, 1.0f, Dr);
-    axis_llr<HALF>(xi, scale, 1.0f, Di);
-    float xbr = 0.f, xbi = 0.f, gm = 0.f, gr = 0.f;
-#pragma unroll
-    for (int bb = 0; bb < HALF; ++bb) {
-        const float sr = axis_llr_slope<HALF>(xr, scale, bb);
-        const float si = axis_llr_slope<HALF>(xi, scale, bb);
-        const float lr = Lbar ? Lbar[bb] : bce_grad(rho * Dr[bb], bits[bb], inv_n);
-        const float li = Lbar ? Lbar[HALF + bb] : bce_grad(rho * Di[bb], bits[HALF + bb], inv_n);
-        xbr = fmaf(lr * rho, sr, xbr);
-        xbi = fmaf(li * rho, si, xbi);
-        gr = fmaf(lr, Dr[bb], fmaf(li, Di[bb], gr));
-        // dx/dmu = -x/mu
-        gm = fmaf(lr * rho * sr, -xr / mu, gm);
-        gm = fmaf(li * rho * si, -xi / mu, gm);
-    }
-    *zbar = make_float2(xbr * s, xbi * s);
-    *dmu = gm;
-    *drho = gr;
-}
-
-// Cross-workgroup hand-off of the partial sums.  The L2 caches of the XCDs are not
-// coherent with each other, and a device-scope release fence would write back a
-// whole L2 (every dirty line, the adjoint's dy included) once per workgroup.  Only
-// the K + 1 partials need to travel, so they bypass the caches instead: they are
-// written with device-scope atomic stores (through to the device's coherence
-// point), the store is waited for (vmcnt 0) before the ticket is taken, and the last
-// workgroup reads them with device-scope atomic loads (through the caches) after
-// its ticket returned.
-constexpr int WAIT_VMEM_ONLY = 0x0F70;   // s_waitcnt vmcnt(0), expcnt and lgkmcnt not waited
-
-__device__ __forceinline__ void store_partial(float *p, float v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ float load_partial(const float *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The last workgroup to take the completion ticket sums every workgroup's K + 1
-// partials in workgroup order (thread t adds workgroups t, t + blockDim, ...;
-// the waves' lanes by a fixed DPP tree; the waves in order), writes dlambda and
-// dbeta, and resets the ticket.  Every thread of the workgroup must call it after
-// storing its share of the workgroup's partials with store_partial.
-__device__ void finish_partials(const Params &P, int K)
-{
-    __shared__ int last;
-    __shared__ float red[8][8];   // [entry of the batch][wave], at most 8 waves
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(WAIT_VMEM_ONLY);   // this thread's partial stores performed
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = __hip_atomic_fetch_add(P.ticket, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        last = t == gridDim.x - 1u;
-    }
-    __syncthreads();
-    if (!last) return;
-    __builtin_amdgcn_s_waitcnt(WAIT_VMEM_ONLY);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const int E = K + 1, nb = gridDim.x;
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    for (int e0 = 0; e0 < E; e0 += 8) {
-        float acc[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = 0.f;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-            const float *pb = P.partials + (size_t)b * E + e0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (e0 + i < E) acc[i] += load_partial(pb + i);
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) acc[i] = wave_sum(acc[i]);
-        if ((threadIdx.x & 63) == 0)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) red[i][wave] = acc[i];
-        __syncthreads();
-        const int e = e0 + (int)threadIdx.x;
-        if (threadIdx.x < 8 && e < E) {
-            float t = 0.f;
-            for (int w = 0; w < nwaves; ++w) t += red[threadIdx.x][w];
-            if (e < K) P.dlambda[e] = t;
-            else *P.dbeta = P.box ? t : 0.f;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) __hip_atomic_store(P.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One adjoint coordinate update (the reverse of update (k, u)): returns the new
-// z_bar_u, accumulates lambda_bar_k and beta_bar, and adds h d^-1 c_bar to r_bar.
-// h: this lane's part of column u; dp = (d_u^-1, p_u); zn = z_u after the update;
-// zbu = z_bar_u before.
-template <int L, int NPL, bool BOX>
-__device__ __forceinline__ float2 adjoint_update(const float2 *h, float2 dp, float2 zn, float2 zbu,
-                                                 float beta, float2 *rb, float &lam_bar,
-                                                 float &beta_bar)
-{
-    const float2 hb = group_sum2<L>(partial_inner<NPL, 2>(h, rb));   // h^H r_bar
-    const float tr = zbu.x - hb.x, ti = zbu.y - hb.y;                // z_bar + Delta_bar
-    float cbr = tr, cbi = ti;
-    if constexpr (BOX) {
-        if (!(fabsf(zn.x) < beta)) { beta_bar += zn.x > 0.f ? tr : -tr; cbr = 0.f; }
-        if (!(fabsf(zn.y) < beta)) { beta_bar += zn.y > 0.f ? ti : -ti; cbi = 0.f; }
-    }
-    lam_bar = fmaf(-dp.x, fmaf(zn.x, cbr, zn.y * cbi), lam_bar);
-    axpy_add<NPL>(h, make_float2(dp.x * cbr, dp.x * cbi), rb);
-    return make_float2(hb.x + dp.y * cbr, hb.y + dp.y * cbi);       // -Delta_bar + p c_bar
-}
-
 // UC > 0: U == UC and the user loop is unrolled: every LDS address of an update is
 // a compile-time offset from one base, and the straight-line sweep lets the
-// compiler read the next column while the current update computes.
-template <int L, int NPL, bool F16, bool BOX, int UC>
+// compiler read the next column while the current update computes.  PREFETCH
+// (UC > 0, launches with few waves per SIMD): that read is issued one update ahead
+// into a second register buffer (same arithmetic).
+template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false>
 __global__ __launch_bounds__(512) void k_backward(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -255,6 +127,8 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
     if (zpre && K >= 2) fetch_row(K - 2);
     __syncthreads();   // z_bar rows of every group written (groups never span waves,
                        // so later row updates need only the wave's own LDS order)
+    float2 hn[NPL];    // PREFETCH: the next update's column (users run backwards)
+    if constexpr (PREFETCH && UC > 0) load_column<L, NPL>(Hs + (UC - 1) * L * NPL, j, hn);
     for (int k = K - 1; k >= 0; --k) {
         if (k < K - 1) {
             if (zpre) {
@@ -275,7 +149,13 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
 #pragma unroll
             for (int u = UC - 1; u >= 0; --u) {
                 float2 h[NPL];
-                load_column<L, NPL>(Hs + u * BP, j, h);
+                if constexpr (PREFETCH) {
+#pragma unroll
+                    for (int i = 0; i < NPL; ++i) h[i] = hn[i];
+                    load_column<L, NPL>(Hs + (u > 0 ? u - 1 : UC - 1) * BP, j, hn);
+                } else {
+                    load_column<L, NPL>(Hs + u * BP, j, h);
+                }
                 zb[u] = adjoint_update<L, NPL, BOX>(h, dpk[u], zv[u], zb[u], beta, rb, lam_bar,
                                                     beta_bar);
             }
@@ -309,34 +189,37 @@ __global__ __launch_bounds__(512) void k_backward(Params P)
         for (int w = 0; w < nwaves; ++w) sum += sm.part[e * nwaves + w];
         store_partial(part_out + e, sum);
     }
-    finish_partials(P, K);
+    finish_partials(P, K + 1);
 }
 
-// Writes dlambda and dbeta from nblocks per-workgroup partials in a fixed order
-// (thread t adds workgroups t, t + 256, ...; fixed cross-lane tree; waves in
-// order).  The adjoint kernel reduces its own partials; this kernel writes the
-// zero gradients of an empty problem (nblocks = 0).
+// Writes dlambda and dbeta (and, with loss, the mean loss) from nblocks
+// per-workgroup partials of E entries in a fixed order (thread t adds workgroups
+// t, t + 256, ...; fixed cross-lane tree; waves in order).  The adjoint and
+// training-step kernels reduce their own partials; this kernel writes the zero
+// gradients and loss of an empty problem (nblocks = 0).
 __global__ __launch_bounds__(256) void k_reduce_partials(const float *partials, int nblocks, int K,
-                                                         int box, float *dlambda, float *dbeta)
+                                                         int E, int box, float inv_nbits,
+                                                         float *dlambda, float *dbeta, float *loss)
 {
     __shared__ float red[4];
-    const int e = blockIdx.x;   // 0..K-1: dlambda, K: dbeta
+    const int e = blockIdx.x;   // 0..K-1: dlambda, K: dbeta, K + 1: loss
     float s = 0.f;
-    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(size_t)b * (K + 1) + e];
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(size_t)b * E + e];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
         const float t = (red[0] + red[1]) + (red[2] + red[3]);
         if (e < K) dlambda[e] = t;
-        else *dbeta = box ? t : 0.f;
+        else if (e == K) *dbeta = box ? t : 0.f;
+        else *loss = t * inv_nbits;
     }
 }
 
-template <int L, int NPL, bool F16, bool BOX, int UC>
+template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false>
 static hipError_t launch_bwd_u(const Params &p, int threads, size_t lds, hipStream_t s)
 {
-    auto fn = k_backward<L, NPL, F16, BOX, UC>;
+    auto fn = k_backward<L, NPL, F16, BOX, UC, PREFETCH>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -359,8 +242,13 @@ template <int L, int NPL, bool F16, bool BOX>
 static hipError_t launch_bwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
 {
     if constexpr (NPL <= 8) {
-        if (p.U == 8) return launch_bwd_u<L, NPL, F16, BOX, 8>(p, threads, lds, s);
-        if (p.U == 16) return launch_bwd_u<L, NPL, F16, BOX, 16>(p, threads, lds, s);
+        const bool few = latency_bound(p, threads);
+        if (p.U == 8)
+            return few ? launch_bwd_u<L, NPL, F16, BOX, 8, true>(p, threads, lds, s)
+                       : launch_bwd_u<L, NPL, F16, BOX, 8>(p, threads, lds, s);
+        if (p.U == 16)
+            return few ? launch_bwd_u<L, NPL, F16, BOX, 16, true>(p, threads, lds, s)
+                       : launch_bwd_u<L, NPL, F16, BOX, 16>(p, threads, lds, s);
     }
     return launch_bwd_u<L, NPL, F16, BOX, 0>(p, threads, lds, s);
 }
@@ -400,10 +288,12 @@ hipError_t launch_backward(int L, int NPL, bool f16, const Params &p, int thread
     }
 }
 
-hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s)
+hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, float *loss,
+                                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(p.K + 1), dim3(256), 0, s, p.partials, p.nblocks,
-                       p.K, p.box, dlambda, dbeta);
+    const int E = p.K + (loss ? 2 : 1);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(E), dim3(256), 0, s, p.partials, p.nblocks, p.K, E,
+                       p.box, p.inv_nbits, dlambda, dbeta, loss);
     return hipGetLastError();
 }
 

@@ -5,14 +5,14 @@
 
 namespace ocd {
 
-template <int L, int NPL, bool F16, bool BOX, int UC>
+template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false>
 __global__ __launch_bounds__(512) void k_forward(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem sm = carve(smem, P, blockDim.x / L, false);
     const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     stagger_loads(P);
-    forward_tile<L, NPL, F16, BOX, UC>(P, sm, tile_of(P, bid));
+    forward_tile<L, NPL, F16, BOX, UC, true, PREFETCH>(P, sm, tile_of(P, bid));
 }
 
 // Standalone preprocessing: a 16-lane group per (subcarrier, user) column, lane l
@@ -48,10 +48,10 @@ __global__ __launch_bounds__(256) void k_preprocess(Params P, float *g, float *d
     }
 }
 
-template <int L, int NPL, bool F16, bool BOX, int UC>
+template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false>
 static hipError_t launch_fwd_u(const Params &p, int threads, size_t lds, hipStream_t s)
 {
-    auto fn = k_forward<L, NPL, F16, BOX, UC>;
+    auto fn = k_forward<L, NPL, F16, BOX, UC, PREFETCH>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -74,8 +74,13 @@ template <int L, int NPL, bool F16, bool BOX>
 static hipError_t launch_fwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
 {
     if constexpr (NPL <= 8) {
-        if (p.U == 8) return launch_fwd_u<L, NPL, F16, BOX, 8>(p, threads, lds, s);
-        if (p.U == 16) return launch_fwd_u<L, NPL, F16, BOX, 16>(p, threads, lds, s);
+        const bool few = latency_bound(p, threads);
+        if (p.U == 8)
+            return few ? launch_fwd_u<L, NPL, F16, BOX, 8, true>(p, threads, lds, s)
+                       : launch_fwd_u<L, NPL, F16, BOX, 8>(p, threads, lds, s);
+        if (p.U == 16)
+            return few ? launch_fwd_u<L, NPL, F16, BOX, 16, true>(p, threads, lds, s)
+                       : launch_fwd_u<L, NPL, F16, BOX, 16>(p, threads, lds, s);
     }
     return launch_fwd_u<L, NPL, F16, BOX, 0>(p, threads, lds, s);
 }

@@ -45,10 +45,11 @@ struct Params {
                                 // dLoss/dLLR itself for the mean BCE of the LLRs
     float inv_nbits;     // 1 / (W S U Q), with bits
     float2 *dy;          // [W][S][B] or nullptr
-    float *partials;     // [nblocks][K + 1]
+    float *partials;     // [nblocks][K + 1] (adjoint), [nblocks][K + 2] (training step)
     unsigned *ticket;    // completion ticket of the adjoint's workgroups (zero between launches)
     float *dlambda;      // [K] adjoint output
     float *dbeta;        // [1] adjoint output
+    float *loss;         // [1] training step: mean cross-entropy of the LLRs, or nullptr
 };
 
 // Unsigned 32-bit division by a divisor d fixed for a launch, as a multiply-high,
@@ -71,8 +72,13 @@ __host__ __device__ inline unsigned divide_invariant(unsigned n, unsigned m, int
     return (t + ((n - t) >> s1)) >> s2;
 }
 
-// Bytes of dynamic LDS a launch of this shape needs.
-inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward, int nwaves = 0)
+// Compute units of the current device (cached per device; 0 on error).
+int device_cu_count();
+
+// Bytes of dynamic LDS a launch of this shape needs (train: the fused training
+// step, which also keeps every vector's K rows of z history and one more partial).
+inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward, int nwaves = 0,
+                        bool train = false)
 {
     const int Kt = p.per_sweep ? p.K : 1;
     size_t b = 0;
@@ -84,8 +90,9 @@ inline size_t lds_bytes(const Params &p, int vpb_cap, bool backward, int nwaves 
     b += (size_t)(p.vpb + 1) * p.U * 8;              // z per vector (+ idle groups' row)
     if (backward) {
         b += (size_t)(p.vpb + 1) * p.U * 8;          // z_bar per vector
-        b += (size_t)(p.K + 1) * (size_t)nwaves * 4; // per-wave partials of every sweep
+        b += (size_t)(p.K + 2) * (size_t)nwaves * 4; // per-wave partials (sweeps, beta, loss)
     }
+    if (train) b += (size_t)(p.vpb + 1) * p.K * p.U * 8;   // z^(k) rows per vector
     return b;
 }
 
@@ -102,8 +109,14 @@ inline size_t mmse_lds_bytes(const Params &p)
     return b;
 }
 
-// Compute units of the current device (cached per device; 0 on error).
-int device_cu_count();
+// A launch with at most two waves per SIMD (the grid's waves over 4 SIMDs per CU)
+// has no other waves to hide a wave's latencies behind: the unrolled sweeps then
+// prefetch their operands one update ahead.
+inline bool latency_bound(const Params &p, int threads)
+{
+    const int cus = device_cu_count();
+    return cus > 0 && (long)p.nblocks * (threads / 64) <= 2L * 4 * cus;
+}
 
 // Launchers (one per template instantiation, selected at run time).
 hipError_t launch_forward(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
@@ -118,6 +131,9 @@ hipError_t launch_mmse_mfma(bool f16, const Params &p, size_t lds, hipStream_t s
 size_t mmse_mfma_lds_bytes(int Kp, int U, int S);
 hipError_t launch_preprocess(bool f16, const Params &p, float *g, float *dinv, float *pp,
                              hipStream_t s);
-hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, hipStream_t s);
+hipError_t launch_reduce_partials(const Params &p, float *dlambda, float *dbeta, float *loss,
+                                  hipStream_t s);
+hipError_t launch_train(int L, int NPL, bool f16, const Params &p, int threads, size_t lds,
+                        hipStream_t s);
 
 }  // namespace ocd

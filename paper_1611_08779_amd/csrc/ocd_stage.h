@@ -14,14 +14,15 @@ struct Smem {
     float2 *lc;    // [maxslots][U]: soft-output coefficients (see llr_coef)
     float2 *z;     // [vpb + 1][U]: current z of each vector; idle groups share the last row
     float2 *zbar;  // [vpb + 1][U]: adjoint only, dLoss/dz
-    float *part;   // [(K + 1) * waves]: adjoint only, per-wave partial sums of every sweep
+    float *part;   // [(K + 2) * waves]: adjoint only, per-wave partial sums (sweeps, beta, loss)
+    float2 *zh;    // [vpb + 1][K][U]: training step only, z after every sweep
 };
 
 // Row of the per-vector LDS arrays used by lane group grp.
 __device__ __forceinline__ int zrow_of(const Params &P, int grp) { return grp < P.vpb ? grp : P.vpb; }
 
 __device__ __forceinline__ Smem carve(unsigned char *smem, const Params &P, int vpb_cap,
-                                      bool backward)
+                                      bool backward, bool train = false)
 {
     const int Kt = P.per_sweep ? P.K : 1;
     Smem s;
@@ -40,6 +41,11 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const Params &P, int 
     off += zrows;
     s.zbar = nullptr;
     s.part = nullptr;
+    s.zh = nullptr;
+    if (train) {   // 8-byte aligned here: before the partials
+        s.zh = reinterpret_cast<float2 *>(smem + off);
+        off += (size_t)(P.vpb + 1) * P.K * P.U * 8;
+    }
     if (backward) {
         s.zbar = reinterpret_cast<float2 *>(smem + off);
         off += zrows;

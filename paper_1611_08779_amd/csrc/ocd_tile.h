@@ -29,7 +29,10 @@ namespace ocd {
 // run-time bound.
 // PIPE: with a run-time U, read the next update's operands while the current
 // one computes (a second operand buffer); off where registers are scarce.
-template <int L, int NPL, bool F16, bool BOX, int UC = 0, bool PIPE = true>
+// PREFETCH (UC > 0): read the next update's column one update ahead, into a
+// second register buffer: the launches with few waves per SIMD have nothing else
+// to hide the LDS latency behind, and the registers to spare (same arithmetic).
+template <int L, int NPL, bool F16, bool BOX, int UC = 0, bool PIPE = true, bool PREFETCH = false>
 __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
 {
     const int U = P.U, Bpad = P.Bpad;
@@ -69,12 +72,20 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
         float2 zr[UC];
 #pragma unroll
         for (int u = 0; u < UC; ++u) zr[u] = make_float2(0.f, 0.f);
+        float2 hn[NPL];   // PREFETCH: the next update's column
+        if constexpr (PREFETCH) load_column<L, NPL>(Hs, j, hn);
         for (int k = 0; k < P.K; ++k) {
             const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
 #pragma unroll
             for (int u = 0; u < UC; ++u) {
                 float2 h[NPL];
-                load_column<L, NPL>(Hs + u * BP, j, h);
+                if constexpr (PREFETCH) {
+#pragma unroll
+                    for (int i = 0; i < NPL; ++i) h[i] = hn[i];
+                    load_column<L, NPL>(Hs + ((u + 1) % UC) * BP, j, hn);
+                } else {
+                    load_column<L, NPL>(Hs + u * BP, j, h);
+                }
                 if (u == UC - 1 && k == P.K - 1)   // r is not read after the last update
                     zr[u] = coordinate_update<L, NPL, BOX, 1, false>(h, dpk[u], zr[u], beta, r);
                 else

@@ -255,9 +255,9 @@ def test_fused_cross_entropy_adjoint(ocd, mode):
 
 
 def test_fused_loss_function_matches_llr_function_plus_torch_loss(ocd):
-    """ocd_bce_loss (forward loss in torch, backward through ocd_detect_backward_bce)
-    gives the loss and the gradients of ocd_llr followed by torch's BCE with logits,
-    including a non-unit upstream gradient."""
+    """ocd_bce_loss (one training-step launch: the loss summed in FP32 in the kernel and
+    its gradients) gives the loss and the gradients of ocd_llr followed by torch's BCE
+    with logits, including a non-unit upstream gradient."""
     from paper_1611_08779_amd.autograd import ocd_bce_loss, ocd_llr
     B, U, W, S, Q, K = 128, 16, 16, 4, 4, 4
     wl = synth.make_workload(B, U, W, S, Q, 10.0, seed=[21, 1])
@@ -279,7 +279,7 @@ def test_fused_loss_function_matches_llr_function_plus_torch_loss(ocd):
         torch.cuda.synchronize()
         grads.append((float(loss.detach()), host(lam.grad), float(host(beta.grad)[0]), host(y.grad)))
     (l0, gl0, gb0, gy0), (l1, gl1, gb1, gy1) = grads
-    assert abs(l1 - l0) <= 1e-6 * abs(l0)
+    assert abs(l1 - l0) <= 1e-5 * abs(l0)
     assert rel(gl1, gl0) <= 1e-4
     assert rel(gy1, gy0) <= 1e-4
     assert abs(gb1 - gb0) <= 1e-4 * max(abs(gb0), 1e-12)
