@@ -413,6 +413,8 @@ def main():
     ap.add_argument("--s1-only", action="store_true",
                     help="only the S=1 form (one H per vector); with --plan L,VPB the register "
                          "plan is fixed instead of autotuned (profiled runs)")
+    ap.add_argument("--jobs-only", action="store_true",
+                    help="only the 48-job batched form")
     ap.add_argument("--fwdbwd-only", action="store_true",
                     help="only the forward+backward step of the differentiable workload "
                          "(profiled runs)")
@@ -454,7 +456,7 @@ def main():
 
     # ---------------------------------------------------------------- headline
     B, U, W, S, Q, K, snr = 128, 8, 1200, 14, 6, 3, 20.0
-    if args.s1_only or args.fwdbwd_only:
+    if args.s1_only or args.fwdbwd_only or args.jobs_only:
         args.slots = 1          # the headline slot only fixes N0
     log("generating %d slots of B=%d U=%d W=%d S=%d (64-QAM, %g dB)" % (args.slots, B, U, W, S, snr))
     slots = [synth.make_workload_device(B, U, W, S, Q, snr, seed=1000 + i, device=dev)
@@ -463,10 +465,12 @@ def main():
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
     outs = [(torch.empty(W, S, U, dtype=torch.complex64, device=dev),
              torch.empty(W, S, U, Q, dtype=torch.float32, device=dev)) for _ in slots]
-    if args.s1_only or args.fwdbwd_only:
+    if args.s1_only or args.fwdbwd_only or args.jobs_only:
         if args.s1_only:
             fixed = [int(x) for x in args.plan.split(",")][:2] if args.plan else None
             res = s1_form(torch, ocd, synth, dev, args, pb, plan=fixed)
+        elif args.jobs_only:
+            res = jobs_form(torch, np, ocd, synth, dev)
         else:
             res = fwd_bwd_form(torch, np, ocd, synth, dev)
         print(json.dumps(res), flush=True)
@@ -892,6 +896,89 @@ def fwd_bwd_form(torch, np, ocd, synth, dev):
     }
 
 
+def jobs_form(torch, np, ocd, synth, dev):
+    """48 uneven jobs (B, U, W, K drawn independently; S = 14, 64-QAM, MMSE): one
+    persistent launch of ocd_detect_jobs (batch-tuned, graph-captured) against one
+    graph-captured launch per job with each job's autotuned plan."""
+    log("form: 48 batched jobs")
+    jl = synth.batched_job_list()
+    probs, Hs, ys = [], [], []
+    for j, jd in enumerate(jl):
+        wl = synth.make_workload_device(jd["B"], jd["U"], jd["W"], jd["S"], jd["Q"], jd["snr_db"],
+                                        seed=3000 + j, device=dev)
+        probs.append(ocd.problem(jd["B"], jd["U"], jd["W"], jd["S"], jd["Q"], jd["K"], "mmse", "f32",
+                                 float(np.float32(wl["N0"]))))
+        Hs.append(wl["H"])
+        ys.append(wl["y"])
+    z, L, ws = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_TUNE)
+    torch.cuda.synchronize()
+    schedule = ocd.ocd_jobs_schedule(probs)
+    log("batched jobs: tuned schedule %s" % schedule)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = 20
+    call = ocd.JobsCall(probs, Hs, ys, z, L, ws, flags=ocd.OCD_JOBS_GRAPH)
+    warm_up(torch, call)
+    ev[0].record()
+    for _ in range(reps):
+        call()
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_batched = ev[0].elapsed_time(ev[1]) / reps
+    # the same launch without the graph (host path included)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        call(flags=0)
+    e1.record()
+    torch.cuda.synchronize()
+    t_batched_eager = e0.elapsed_time(e1) / reps
+    # one launch per job, each with its own autotuned plan, captured in a graph
+    zs = [torch.empty_like(t) for t in z]
+    Ls = [torch.empty_like(t) for t in L]
+    for j, pbj in enumerate(probs):
+        ocd.ocd_autotune(pbj, Hs[j], ys[j], zs[j], Ls[j], repeats=2)
+    fns = [(lambda j=j: ocd.ocd_detect(probs[j], Hs[j], ys[j], z=zs[j], llr=Ls[j]))
+           for j in range(len(probs))]
+    gs = GraphedSteps(torch, fns)
+    warm_up(torch, gs.replay)
+    ev[2].record()
+    for _ in range(reps):
+        gs.replay()
+    ev[3].record()
+    torch.cuda.synchronize()
+    t_sep = ev[2].elapsed_time(ev[3]) / reps
+    # eager per-job launches (what a caller without graphs gets)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        for f in fns:
+            f()
+    e1.record()
+    torch.cuda.synchronize()
+    t_eager = e0.elapsed_time(e1) / reps
+    agree = all(torch.allclose(z[j], zs[j], rtol=1e-5, atol=1e-6) for j in range(len(probs)))
+    total_bits = sum(p.W * p.S * p.U * p.Q for p in probs)
+    total_flops = sum(algorithmic(p.B, p.U, p.S, p.K, p.Q)[0] * p.W * p.S for p in probs)
+    res = {
+        "ms_one_launch_graph": t_batched, "ms_one_launch_eager": t_batched_eager,
+        "ms_per_job_launches_graph": t_sep,
+        "ms_per_job_launches_eager": t_eager,
+        "speedup_vs_per_job_graph": t_sep / t_batched, "speedup_vs_per_job_eager": t_eager / t_batched,
+        "gbps_one_launch": total_bits / (t_batched / 1e3) / 1e9, "results_agree": bool(agree),
+        "tflops_one_launch": total_flops / (t_batched / 1e3) / 1e12,
+        "jobs": len(probs), "vectors": sum(p.W * p.S for p in probs),
+        "schedule": {"persistent": bool(schedule["persistent"]),
+                     "tile_policy": ["512/L vectors", "whole subcarriers", "half-size"][
+                         schedule["tile_policy"]],
+                     "lane_mode": ["8 entries per lane", "16 per lane for B > 128",
+                                   "16 for B > 128, 4 for 32 < B <= 128"][schedule["lane_mode"]],
+                     "chosen_by": "ocd_detect_jobs' batch tuner (OCD_JOBS_TUNE)"},
+    }
+    del Hs, ys, z, L, zs, Ls, ws, gs, call
+    return res
+
+
+
 def slots_per_launch_form(torch, ocd, synth, dev, pb32, plan):
     """The headline detection with n slots' subcarriers in one launch (W = 1200 n,
     n = 1, 2, 4, 8), same plan, graph replays over 4 distinct inputs: how much of a
@@ -969,81 +1056,7 @@ def other_forms(torch, np, ocd, synth, dev, args, slots, pb32, t32, gbps32):
     forms["s1_one_H_per_vector"] = s1_form(torch, ocd, synth, dev, args, pb32)
 
     # ---- 48 uneven jobs: one persistent graph launch vs one launch per job
-    log("form: 48 batched jobs")
-    jl = synth.batched_job_list()
-    probs, Hs, ys = [], [], []
-    for j, jd in enumerate(jl):
-        wl = synth.make_workload_device(jd["B"], jd["U"], jd["W"], jd["S"], jd["Q"], jd["snr_db"],
-                                        seed=3000 + j, device=dev)
-        probs.append(ocd.problem(jd["B"], jd["U"], jd["W"], jd["S"], jd["Q"], jd["K"], "mmse", "f32",
-                                 float(np.float32(wl["N0"]))))
-        Hs.append(wl["H"])
-        ys.append(wl["y"])
-    z, L, ws = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_TUNE)
-    torch.cuda.synchronize()
-    schedule = ocd.ocd_jobs_schedule(probs)
-    log("batched jobs: tuned schedule %s" % schedule)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    reps = 20
-    call = ocd.JobsCall(probs, Hs, ys, z, L, ws, flags=ocd.OCD_JOBS_GRAPH)
-    warm_up(torch, call)
-    ev[0].record()
-    for _ in range(reps):
-        call()
-    ev[1].record()
-    torch.cuda.synchronize()
-    t_batched = ev[0].elapsed_time(ev[1]) / reps
-    # the same launch without the graph (host path included)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        call(flags=0)
-    e1.record()
-    torch.cuda.synchronize()
-    t_batched_eager = e0.elapsed_time(e1) / reps
-    # one launch per job, each with its own autotuned plan, captured in a graph
-    zs = [torch.empty_like(t) for t in z]
-    Ls = [torch.empty_like(t) for t in L]
-    for j, pbj in enumerate(probs):
-        ocd.ocd_autotune(pbj, Hs[j], ys[j], zs[j], Ls[j], repeats=2)
-    fns = [(lambda j=j: ocd.ocd_detect(probs[j], Hs[j], ys[j], z=zs[j], llr=Ls[j]))
-           for j in range(len(probs))]
-    gs = GraphedSteps(torch, fns)
-    warm_up(torch, gs.replay)
-    ev[2].record()
-    for _ in range(reps):
-        gs.replay()
-    ev[3].record()
-    torch.cuda.synchronize()
-    t_sep = ev[2].elapsed_time(ev[3]) / reps
-    # eager per-job launches (what a caller without graphs gets)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        for f in fns:
-            f()
-    e1.record()
-    torch.cuda.synchronize()
-    t_eager = e0.elapsed_time(e1) / reps
-    agree = all(torch.allclose(z[j], zs[j], rtol=1e-5, atol=1e-6) for j in range(len(probs)))
-    total_bits = sum(p.W * p.S * p.U * p.Q for p in probs)
-    total_flops = sum(algorithmic(p.B, p.U, p.S, p.K, p.Q)[0] * p.W * p.S for p in probs)
-    forms["batched_48_jobs"] = {
-        "ms_one_launch_graph": t_batched, "ms_one_launch_eager": t_batched_eager,
-        "ms_per_job_launches_graph": t_sep,
-        "ms_per_job_launches_eager": t_eager,
-        "speedup_vs_per_job_graph": t_sep / t_batched, "speedup_vs_per_job_eager": t_eager / t_batched,
-        "gbps_one_launch": total_bits / (t_batched / 1e3) / 1e9, "results_agree": bool(agree),
-        "tflops_one_launch": total_flops / (t_batched / 1e3) / 1e12,
-        "jobs": len(probs), "vectors": sum(p.W * p.S for p in probs),
-        "schedule": {"persistent": bool(schedule["persistent"]),
-                     "tile_policy": ["512/L vectors", "whole subcarriers", "half-size"][
-                         schedule["tile_policy"]],
-                     "lane_mode": ["8 entries per lane", "16 per lane for B > 128",
-                                   "16 for B > 128, 4 for 32 < B <= 128"][schedule["lane_mode"]],
-                     "chosen_by": "ocd_detect_jobs' batch tuner (OCD_JOBS_TUNE)"},
-    }
-    del Hs, ys, z, L, zs, Ls, ws, gs, call
+    forms["batched_48_jobs"] = jobs_form(torch, np, ocd, synth, dev)
 
     # ---- differentiable form: forward + backward step (B=128, U=16, 2048 x 4, 16-QAM, K=4)
     forms["fwd_bwd_differentiable"] = fwd_bwd_form(torch, np, ocd, synth, dev)

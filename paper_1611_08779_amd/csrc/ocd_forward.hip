@@ -5,14 +5,14 @@
 
 namespace ocd {
 
-template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false>
+template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false, bool CHUNKED = false>
 __global__ __launch_bounds__(512) void k_forward(Params P)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Smem sm = carve(smem, P, blockDim.x / L, false);
     const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     stagger_loads(P);
-    forward_tile<L, NPL, F16, BOX, UC, true, PREFETCH>(P, sm, tile_of(P, bid));
+    forward_tile<L, NPL, F16, BOX, UC, true, PREFETCH, CHUNKED>(P, sm, tile_of(P, bid));
 }
 
 // Standalone preprocessing: a 16-lane group per (subcarrier, user) column, lane l
@@ -48,10 +48,10 @@ __global__ __launch_bounds__(256) void k_preprocess(Params P, float *g, float *d
     }
 }
 
-template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false>
+template <int L, int NPL, bool F16, bool BOX, int UC, bool PREFETCH = false, bool CHUNKED = false>
 static hipError_t launch_fwd_u(const Params &p, int threads, size_t lds, hipStream_t s)
 {
-    auto fn = k_forward<L, NPL, F16, BOX, UC, PREFETCH>;
+    auto fn = k_forward<L, NPL, F16, BOX, UC, PREFETCH, CHUNKED>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -69,7 +69,8 @@ static hipError_t launch_fwd_u(const Params &p, int threads, size_t lds, hipStre
     return hipGetLastError();
 }
 
-// Exactly 8 or 16 users with at most 8 entries per lane take the unrolled user loop.
+// Exactly 8 or 16 users with at most 8 entries per lane take the unrolled user loop,
+// other multiples of 8 users its chunked form.
 template <int L, int NPL, bool F16, bool BOX>
 static hipError_t launch_fwd_t(const Params &p, int threads, size_t lds, hipStream_t s)
 {
@@ -81,6 +82,8 @@ static hipError_t launch_fwd_t(const Params &p, int threads, size_t lds, hipStre
         if (p.U == 16)
             return few ? launch_fwd_u<L, NPL, F16, BOX, 16, true>(p, threads, lds, s)
                        : launch_fwd_u<L, NPL, F16, BOX, 16>(p, threads, lds, s);
+        if (p.U % 8 == 0)
+            return launch_fwd_u<L, NPL, F16, BOX, 8, false, true>(p, threads, lds, s);
     }
     return launch_fwd_u<L, NPL, F16, BOX, 0>(p, threads, lds, s);
 }

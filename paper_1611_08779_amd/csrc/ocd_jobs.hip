@@ -8,7 +8,8 @@
 // B >= 256 (half the lanes per vector: no reduction across DPP rows) and 8 for
 // the others; or in addition NPL = 4 for jobs with B <= 128 (more, shorter lane
 // groups).  Exactly 8 users (16 with 4 entries per lane) take the unrolled user
-// loop.  A tile of whole
+// loop, other multiples of 8 users (at most 8 entries per lane) its chunked form.
+// A tile of whole
 // subcarriers fills most of a 512-lane workgroup whatever B is, while its H_w
 // slots stay within one LDS budget (two tiles per CU).  Tiles are sorted
 // longest-first (LPT) and persistent workgroups pop them from a device counter
@@ -68,10 +69,11 @@ constexpr size_t HEADER_BYTES = 256;
 //   persistent = 1: a fixed grid; each workgroup claims its next tile from the
 //                   queue head while it works on the current one.  Every
 //                   workgroup stops when the queue is exhausted.
-template <int L, int NPL, int UC, bool F16, bool BOX>
+template <int L, int NPL, int UC, bool F16, bool BOX, bool CHUNKED = false>
 __device__ __forceinline__ void job_tile(const Params &P, unsigned char *smem, const Tile &t)
 {
-    forward_tile<L, NPL, F16, BOX, UC, false>(P, carve(smem, P, JOB_THREADS / L, false), t);
+    forward_tile<L, NPL, F16, BOX, UC, false, false, CHUNKED>(
+        P, carve(smem, P, JOB_THREADS / L, false), t);
 }
 
 template <bool F16, bool BOX>
@@ -104,10 +106,12 @@ __global__ __launch_bounds__(JOB_THREADS, 4) void k_jobs(const JobDesc *__restri
         t.w_first = t.vbase / P.S;
         t.nslots = (t.vbase + t.nvb - 1) / P.S - t.w_first + 1;
         // the unrolled user loop for U = 8 (and U = 16 with 4 entries per lane: with 8,
-        // its registers would not fit the budget of four 512-thread workgroups per CU);
+        // its registers would not fit the budget of four 512-thread workgroups per CU),
+        // its chunked form (code 1) for the other multiples of 8 users;
         // plan_jobs builds only the (L, NPL) pairs below (job_shape_built)
         const int npl = jd.npl;
-        const int uc = (P.U == 8 && npl <= 8) || (P.U == 16 && npl == 4) ? P.U : 0;
+        const int uc = (P.U == 8 && npl <= 8) || (P.U == 16 && npl == 4) ? P.U
+                       : (P.U % 8 == 0 && npl <= 8) ? 1 : 0;
         switch (jd.L * 10000 + npl * 100 + uc) {
         case 40800: job_tile<4, 8, 0, F16, BOX>(P, smem, t); break;
         case 40808: job_tile<4, 8, 8, F16, BOX>(P, smem, t); break;
@@ -125,6 +129,12 @@ __global__ __launch_bounds__(JOB_THREADS, 4) void k_jobs(const JobDesc *__restri
         case 320416: job_tile<32, 4, 16, F16, BOX>(P, smem, t); break;
         case 161600: job_tile<16, 16, 0, F16, BOX>(P, smem, t); break;
         case 321600: job_tile<32, 16, 0, F16, BOX>(P, smem, t); break;
+        case 40801: job_tile<4, 8, 8, F16, BOX, true>(P, smem, t); break;
+        case 80801: job_tile<8, 8, 8, F16, BOX, true>(P, smem, t); break;
+        case 160801: job_tile<16, 8, 8, F16, BOX, true>(P, smem, t); break;
+        case 320801: job_tile<32, 8, 8, F16, BOX, true>(P, smem, t); break;
+        case 160401: job_tile<16, 4, 8, F16, BOX, true>(P, smem, t); break;
+        case 320401: job_tile<32, 4, 8, F16, BOX, true>(P, smem, t); break;
         default: break;   // not built: plan_jobs never produces such a job
         }
         if (!persistent) break;

@@ -32,7 +32,12 @@ namespace ocd {
 // PREFETCH (UC > 0): read the next update's column one update ahead, into a
 // second register buffer: the launches with few waves per SIMD have nothing else
 // to hide the LDS latency behind, and the registers to spare (same arithmetic).
-template <int L, int NPL, bool F16, bool BOX, int UC = 0, bool PIPE = true, bool PREFETCH = false>
+// CHUNKED (UC > 0): U is a multiple of UC and the sweep runs as U / UC unrolled
+// chunks of UC users with z in LDS (one more LDS read and write per update, no
+// registers per user): the straight-line chunk keeps the compile-time LDS offsets
+// and the early column reads of the unrolled loop for any such U.
+template <int L, int NPL, bool F16, bool BOX, int UC = 0, bool PIPE = true, bool PREFETCH = false,
+          bool CHUNKED = false>
 __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
 {
     const int U = P.U, Bpad = P.Bpad;
@@ -67,7 +72,29 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
         if (P.z_hist && active)
             for (int u = j; u < U; u += L) P.z_hist[((long)v * P.K + k) * U + u] = zv[u];
     };
-    if constexpr (UC > 0) {
+    if constexpr (UC > 0 && CHUNKED) {
+        constexpr int BP = L * NPL;
+        for (int k = 0; k < P.K; ++k) {
+            const float2 *dpk = dps + (P.per_sweep ? k : 0) * U;
+            const bool last_sweep = k == P.K - 1;
+            for (int c = 0; c < U; c += UC) {
+                const float2 *Hc = Hs + (size_t)c * BP;
+                const float2 *dpc = dpk + c;
+                float2 *zc = zv + c;
+                const bool last_chunk = last_sweep && c + UC == U;
+#pragma unroll
+                for (int u = 0; u < UC; ++u) {
+                    float2 h[NPL];
+                    load_column<L, NPL>(Hc + u * BP, j, h);
+                    if (u == UC - 1 && last_chunk)   // r is not read after the last update
+                        zc[u] = coordinate_update<L, NPL, BOX, 1, false>(h, dpc[u], zc[u], beta, r);
+                    else
+                        zc[u] = coordinate_update<L, NPL, BOX>(h, dpc[u], zc[u], beta, r);
+                }
+            }
+            sweep_done(k);
+        }
+    } else if constexpr (UC > 0) {
         constexpr int BP = L * NPL;
         float2 zr[UC];
 #pragma unroll

@@ -61,6 +61,21 @@ def test_b32_u8_every_plan(ocd, plan):
     run_and_compare(ocd, 32, 8, 64, 1, 4, 3, "mmse", 10.0, [1, 0, 0], hist=True, plan=plan)
 
 
+# multiples of 8 users with at most 8 entries per lane beyond U = 16: the sweep runs
+# as unrolled chunks of 8 users (3 and 4 chunks; at most 32 users), with the per-sweep
+# history
+@pytest.mark.parametrize("case", [
+    (64, 24, 9, 3, 4, 3, "box", (8, 16, 0)),
+    (128, 32, 5, 4, 6, 2, "mmse", (16, 8, 1)),
+    (100, 24, 6, 2, 2, 3, "box", (16, 4, 0)),
+    (256, 32, 3, 5, 4, 5, "box", (32, 5, 0, 0, 1)),
+])
+def test_chunked_user_loop(ocd, case):
+    B, U, W, S, Q, K, mode, plan = case
+    run_and_compare(ocd, B, U, W, S, Q, K, mode, 15.0, [1, 7, U], beta=0.9 * 3 / np.sqrt(10),
+                    hist=True, plan=plan)
+
+
 def test_b32_u8_default_plan(ocd):
     # W differs from the forced-plan cases above, so the heuristic plan is used
     run_and_compare(ocd, 32, 8, 63, 1, 4, 3, "mmse", 10.0, [1, 0, 1], hist=True)
