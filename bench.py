@@ -871,7 +871,8 @@ def fwd_bwd_form(torch, np, ocd, synth, dev):
     train_agree = all(float((a - b).abs().max()) <= 1e-4 * max(float(b.abs().max()), 1e-30)
                       for a, b in zip((dlam, dbeta, dy), ref))
     train_agree = train_agree and abs(float(loss1) - loss_ref) <= 1e-5 * loss_ref
-    plan_t = ocd.ocd_train_plan(pb5)
+    plan_t = ocd.ocd_autotune_train(pb5, wl["H"], wl["y"], lam, bits_u8, loss1, dlam, dbeta, dy,
+                                    wsb, repeats=3)
     tts, _ = time_graph(torch, GraphedSteps(torch, [train_step] * 8), 400, 16)
     tfb, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd_fused] * 8), 400, 16)
     tfb2, _ = time_graph(torch, GraphedSteps(torch, [fwd_bwd] * 8), 400, 16)

@@ -179,9 +179,9 @@ ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void *H, const v
  *   z, llr      outputs as in ocd_detect, each may be NULL (not written)
  *   loss        device [1], the mean cross-entropy (overwritten; 0 when W = 0)
  *   dlambda, dbeta, dy, workspace   as in ocd_detect_backward (dy may be NULL)
- * The plan is the adjoint's (ocd_autotune_backward's cached one, else the heuristic
- * one) with its vectors per workgroup halved until the z history fits in LDS; see
- * ocd_train_plan.  Returns OCD_EINVAL for a NULL loss, dlambda or dbeta, for NULL H, y
+ * The plan is the one ocd_autotune_train cached for the shape, else the adjoint's
+ * (ocd_autotune_backward's cached one, else the heuristic one) with its vectors per
+ * workgroup halved until the z history fits in LDS; see ocd_train_plan.  Returns OCD_EINVAL for a NULL loss, dlambda or dbeta, for NULL H, y
  * or bits when W > 0, and for a workspace that is too small or not 16-byte aligned. */
 ocd_status ocd_detect_train_bce(const ocd_problem *pb, const void *H, const void *y,
                                 const float *lambda, const uint8_t *bits, float *z, float *llr,
@@ -259,6 +259,17 @@ ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
  * to that JSON file, keyed by GPU architecture and shape. */
 ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,
                         float *z, float *llr, int repeats, ocd_plan *best, hipStream_t stream);
+
+/* Autotuner of the training step: times every valid plan of ocd_detect_train_bce
+ * (those whose z history fits in LDS, then the staggered staging on the fastest)
+ * on the caller's buffers (loss, dlambda, dbeta, dy are overwritten; z and the LLRs
+ * are not written; the other arguments are those of ocd_detect_train_bce), caches
+ * the fastest for the shape and returns it.  Synchronises `stream`. */
+ocd_status ocd_autotune_train(const ocd_problem *pb, const void *H, const void *y,
+                              const float *lambda, const uint8_t *bits, float *loss,
+                              float *dlambda, float *dbeta, float *dy, void *workspace,
+                              size_t workspace_bytes, int repeats, ocd_plan *best,
+                              hipStream_t stream);
 
 /* Autotuner of the adjoint: times every valid plan of ocd_detect_backward on the
  * caller's buffers (the outputs dlambda, dbeta, dy are overwritten; the other

@@ -32,6 +32,7 @@ __all__ = [
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_detect_backward_bce",
     "ocd_detect_backward_bce_noalloc", "ocd_detect_train_bce", "ocd_train_plan",
+    "ocd_autotune_train",
     "ocd_get_plan", "ocd_set_plan",
     "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
     "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed", "ocd_ofdm_demodulate",
@@ -120,6 +121,8 @@ def _load():
         "ocd_detect_train_bce": ([P, vp, vp, fp, vp, fp, fp, fp, fp, fp, fp, vp, sz, vp],
                                  ctypes.c_int),
         "ocd_train_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
+        "ocd_autotune_train": ([P, vp, vp, fp, vp, fp, fp, fp, fp, vp, sz, ctypes.c_int,
+                                ctypes.POINTER(Plan), vp], ctypes.c_int),
         "ocd_get_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_set_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_autotune": ([P, vp, vp, fp, fp, ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
@@ -320,6 +323,29 @@ def ocd_detect_train_bce(pb: Problem, H, y, lam, bits, z, llr, loss, dlam, dbeta
         _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
         _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, _stream(stream))
     _check("ocd_detect_train_bce", st)
+
+
+def ocd_autotune_train(pb: Problem, H, y, lam, bits, loss, dlam, dbeta, dy, workspace, repeats=5,
+                       stream=None) -> Plan:
+    """Times the valid training-step plans, caches the fastest for the shape."""
+    dev = H.device
+    f32 = (torch.float32,)
+    zt = (torch.complex64, torch.float32)
+    ws_need = ocd_backward_workspace_bytes(pb)
+    best = Plan()
+    st = _lib.ocd_autotune_train(
+        ctypes.byref(pb), _dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb)),
+        _dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev),
+        _dev_ptr(lam, "lam", f32, pb.K * 4, dev),
+        _dev_ptr(bits, "bits", (torch.uint8,), pb.W * pb.S * pb.U * pb.Q, dev),
+        _dev_ptr(loss, "loss", f32, 4, dev),
+        _dev_ptr(dlam, "dlam", f32, pb.K * 4, dev),
+        _dev_ptr(dbeta, "dbeta", f32, 4, dev),
+        _dev_ptr(dy, "dy", zt, pb.W * pb.S * pb.B * 8, dev),
+        _dev_ptr(workspace, "workspace", (torch.uint8,), ws_need, dev), ws_need, int(repeats),
+        ctypes.byref(best), _stream(stream))
+    _check("ocd_autotune_train", st)
+    return best
 
 
 def ocd_train_plan(pb: Problem) -> Plan:

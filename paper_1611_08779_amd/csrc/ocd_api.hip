@@ -244,13 +244,18 @@ static std::mutex g_plan_mu;
 static std::map<std::string, ocd_plan, std::less<>> g_plans;   // lookups take a string_view
 static bool g_plans_loaded = false;
 
-PlanKey plan_key(const ocd_problem *pb, bool per_sweep, bool backward)
+PlanKey plan_key_dir(const ocd_problem *pb, bool per_sweep, const char *dir)
 {
     PlanKey k;
-    std::snprintf(k.s, sizeof k.s, "%s|%s|B%d|U%d|W%d|S%d|K%d|Q%d|m%d|s%d|l%d", arch_name(),
-                  backward ? "bwd" : "fwd", pb->B, pb->U, pb->W, pb->S, pb->K, pb->Q, pb->mode,
-                  pb->storage, per_sweep ? 1 : 0);
+    std::snprintf(k.s, sizeof k.s, "%s|%s|B%d|U%d|W%d|S%d|K%d|Q%d|m%d|s%d|l%d", arch_name(), dir,
+                  pb->B, pb->U, pb->W, pb->S, pb->K, pb->Q, pb->mode, pb->storage,
+                  per_sweep ? 1 : 0);
     return k;
+}
+
+PlanKey plan_key(const ocd_problem *pb, bool per_sweep, bool backward)
+{
+    return plan_key_dir(pb, per_sweep, backward ? "bwd" : "fwd");
 }
 
 static void load_plan_file_locked()
@@ -701,18 +706,32 @@ extern "C" ocd_status ocd_detect_backward_bce(const ocd_problem *pb, const void 
 
 namespace ocd {
 
-// A training-step launch takes the adjoint's plan; each vector's K rows of z
-// history join its LDS, so the vectors per workgroup are halved until they fit.
-static bool make_train_params(const ocd_problem *pb, ocd_plan pl, const float *lambda, Params &P,
-                              int &npl, int &threads, size_t &lds, ocd_plan *used)
+// Parameters of a training-step launch of plan pl: the adjoint's, with each
+// vector's K rows of z history in LDS as well; false if that does not fit.
+static bool train_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda, Params &P,
+                         int &npl, int &threads, size_t &lds)
 {
+    if (!make_params(pb, pl, lambda, true, P, npl, threads, lds)) return false;
+    lds = lds_bytes(P, threads / pl.lanes_per_vector, true, threads / 64, true);
+    return lds <= (size_t)lds_limit_bytes();
+}
+
+// The training step's plan: the one ocd_autotune_train cached for the shape, else
+// the adjoint's with its vectors per workgroup halved until the z history fits.
+static bool choose_train_params(const ocd_problem *pb, const float *lambda, Params &P, int &npl,
+                                int &threads, size_t &lds, ocd_plan *used)
+{
+    ocd_plan pl;
+    if (cached_plan(plan_key_dir(pb, lambda != nullptr, "trn"), pl) &&
+        train_params(pb, pl, lambda, P, npl, threads, lds)) {
+        if (used) *used = pl;
+        return true;
+    }
+    pl = choose_plan(pb, lambda, true);
     for (;;) {
-        if (make_params(pb, pl, lambda, true, P, npl, threads, lds)) {
-            lds = lds_bytes(P, threads / pl.lanes_per_vector, true, threads / 64, true);
-            if (lds <= (size_t)lds_limit_bytes()) {
-                if (used) *used = pl;
-                return true;
-            }
+        if (train_params(pb, pl, lambda, P, npl, threads, lds)) {
+            if (used) *used = pl;
+            return true;
         }
         if (pl.vectors_per_block <= 1) return false;
         pl.vectors_per_block /= 2;
@@ -729,16 +748,15 @@ extern "C" ocd_status ocd_train_plan(const ocd_problem *pb, ocd_plan *plan)
     Params P;
     int npl, threads;
     size_t lds;
-    if (!make_train_params(pb, choose_plan(pb, nullptr, true), nullptr, P, npl, threads, lds, plan))
-        return OCD_EUNSUPPORTED;
+    if (!choose_train_params(pb, nullptr, P, npl, threads, lds, plan)) return OCD_EUNSUPPORTED;
     return OCD_OK;
 }
 
-extern "C" ocd_status ocd_detect_train_bce(const ocd_problem *pb, const void *H, const void *y,
-                                           const float *lambda, const uint8_t *bits, float *z,
-                                           float *llr, float *loss, float *dlambda, float *dbeta,
-                                           float *dy, void *workspace, size_t workspace_bytes,
-                                           hipStream_t stream)
+namespace ocd {
+
+static ocd_status check_train_args(const ocd_problem *pb, const void *H, const void *y,
+                                   const uint8_t *bits, float *loss, float *dlambda, float *dbeta,
+                                   void *workspace, size_t workspace_bytes)
 {
     ocd_status st = validate(pb);
     if (st != OCD_OK) return st;
@@ -746,12 +764,16 @@ extern "C" ocd_status ocd_detect_train_bce(const ocd_problem *pb, const void *H,
     if (pb->W > 0 && (!H || !y || !bits)) return OCD_EINVAL;
     if (workspace_bytes < ocd_backward_workspace_bytes(pb) || !workspace) return OCD_EINVAL;
     if (reinterpret_cast<uintptr_t>(workspace) % 16) return OCD_EINVAL;
-    Params P;
-    int npl, threads;
-    size_t lds;
-    ocd_plan pl;
-    if (!make_train_params(pb, choose_plan(pb, lambda, true), lambda, P, npl, threads, lds, &pl))
-        return OCD_EUNSUPPORTED;
+    return OCD_OK;
+}
+
+// One training-step launch with the parameters P of its plan (lanes per vector L,
+// npl complex entries per lane).
+static ocd_status run_train(const ocd_problem *pb, Params P, int L, int npl, int threads,
+                            size_t lds, const void *H, const void *y, const uint8_t *bits,
+                            float *z, float *llr, float *loss, float *dlambda, float *dbeta,
+                            float *dy, void *workspace, hipStream_t stream)
+{
     P.H = H; P.y = y;
     P.bits = bits;
     const double nbits = (double)pb->W * pb->S * pb->U * pb->Q;
@@ -767,13 +789,120 @@ extern "C" ocd_status ocd_detect_train_bce(const ocd_problem *pb, const void *H,
     set_vec_ok(P, pb, H, y);
     hipError_t e;
     if (pb->W > 0) {
-        e = launch_train(pl.lanes_per_vector, npl, pb->storage == OCD_STORE_F16, P, threads, lds,
-                         stream);
+        e = launch_train(L, npl, pb->storage == OCD_STORE_F16, P, threads, lds, stream);
     } else {
         P.nblocks = 0;   // no workgroups: zero gradients and loss
         e = launch_reduce_partials(P, dlambda, dbeta, loss, stream);
     }
     return e == hipSuccess ? OCD_OK : OCD_EDEVICE;
+}
+
+}  // namespace ocd
+
+extern "C" ocd_status ocd_detect_train_bce(const ocd_problem *pb, const void *H, const void *y,
+                                           const float *lambda, const uint8_t *bits, float *z,
+                                           float *llr, float *loss, float *dlambda, float *dbeta,
+                                           float *dy, void *workspace, size_t workspace_bytes,
+                                           hipStream_t stream)
+{
+    ocd_status st = check_train_args(pb, H, y, bits, loss, dlambda, dbeta, workspace,
+                                     workspace_bytes);
+    if (st != OCD_OK) return st;
+    Params P;
+    int npl, threads;
+    size_t lds;
+    ocd_plan pl;
+    if (!choose_train_params(pb, lambda, P, npl, threads, lds, &pl)) return OCD_EUNSUPPORTED;
+    P.lambda = lambda;
+    return run_train(pb, P, pl.lanes_per_vector, npl, threads, lds, H, y, bits, z, llr, loss,
+                     dlambda, dbeta, dy, workspace, stream);
+}
+
+extern "C" ocd_status ocd_autotune_train(const ocd_problem *pb, const void *H, const void *y,
+                                         const float *lambda, const uint8_t *bits, float *loss,
+                                         float *dlambda, float *dbeta, float *dy, void *workspace,
+                                         size_t workspace_bytes, int repeats, ocd_plan *best,
+                                         hipStream_t stream)
+{
+    ocd_status st = check_train_args(pb, H, y, bits, loss, dlambda, dbeta, workspace,
+                                     workspace_bytes);
+    if (st != OCD_OK) return st;
+    if (!best) return OCD_EINVAL;
+    if (pb->W == 0) {
+        Params P;
+        int npl, threads;
+        size_t lds;
+        if (!choose_train_params(pb, lambda, P, npl, threads, lds, best)) return OCD_EUNSUPPORTED;
+        return OCD_OK;
+    }
+    repeats = std::max(1, std::min(repeats, 100));
+    std::vector<ocd_plan> cands;
+    for (int L : {4, 8, 16, 32}) {
+        const int cap = 512 / L;
+        std::vector<int> vs;
+        for (int v = cap; v >= 1 && v >= cap / 16; v /= 2) vs.push_back(v);
+        if (pb->S > 1)
+            for (int m = pb->S; m <= cap && m <= 4 * pb->S; m += pb->S) vs.push_back(m);
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        for (int v : vs)
+            for (int x : {0, 1}) {
+                ocd_plan pl = {L, v, x, 0, 0};
+                Params P;
+                int npl, threads;
+                size_t lds;
+                if (train_params(pb, pl, lambda, P, npl, threads, lds)) cands.push_back(pl);
+            }
+    }
+    if (cands.empty()) return OCD_EUNSUPPORTED;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return OCD_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OCD_EDEVICE; }
+    auto time_plan = [&](const ocd_plan &pl, float *ms) -> ocd_status {
+        Params P;
+        int npl, threads;
+        size_t lds;
+        if (!train_params(pb, pl, lambda, P, npl, threads, lds)) return OCD_EUNSUPPORTED;
+        P.lambda = lambda;
+        ocd_status s2 = run_train(pb, P, pl.lanes_per_vector, npl, threads, lds, H, y, bits,
+                                  nullptr, nullptr, loss, dlambda, dbeta, dy, workspace, stream);
+        if (s2 != OCD_OK) return s2;
+        (void)hipEventRecord(e0, stream);
+        for (int i = 0; i < repeats && s2 == OCD_OK; ++i)
+            s2 = run_train(pb, P, pl.lanes_per_vector, npl, threads, lds, H, y, bits, nullptr,
+                           nullptr, loss, dlambda, dbeta, dy, workspace, stream);
+        (void)hipEventRecord(e1, stream);
+        if (s2 != OCD_OK || hipEventSynchronize(e1) != hipSuccess) return OCD_EDEVICE;
+        (void)hipEventElapsedTime(ms, e0, e1);
+        return OCD_OK;
+    };
+    float best_ms = 1e30f;
+    ocd_plan best_pl = cands[0];
+    for (const ocd_plan &pl : cands) {
+        float ms = 0.f;
+        st = time_plan(pl, &ms);
+        if (st != OCD_OK) break;
+        if (ms < best_ms) { best_ms = ms; best_pl = pl; }
+    }
+    // second stage: the staggered staging on the fastest plan
+    if (st == OCD_OK) {
+        const ocd_plan base = best_pl;
+        for (int sg : {1, 2, 4}) {
+            ocd_plan pl = base;
+            pl.stagger = sg;
+            float ms = 0.f;
+            st = time_plan(pl, &ms);
+            if (st != OCD_OK) break;
+            if (ms < best_ms) { best_ms = ms; best_pl = pl; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != OCD_OK) return st;
+    store_plan(plan_key_dir(pb, false, "trn"), best_pl, true);
+    store_plan(plan_key_dir(pb, true, "trn"), best_pl, true);
+    *best = best_pl;
+    return OCD_OK;
 }
 
 // ------------------------------------------------------------------ adjoint without allocation

@@ -25,6 +25,7 @@ struct PlanKey {
     char s[192];
 };
 PlanKey plan_key(const ocd_problem *pb, bool per_sweep, bool backward);
+PlanKey plan_key_dir(const ocd_problem *pb, bool per_sweep, const char *dir);
 bool cached_plan(const PlanKey &key, ocd_plan &pl);
 void store_plan(const PlanKey &key, const ocd_plan &pl, bool persist);
 ocd_status run_forward(const ocd_problem *pb, const ocd_plan &pl, const void *H, const void *y,

@@ -205,6 +205,32 @@ def test_train_step_empty_problem_and_null_outputs(ocd):
     assert int(host(ws[:4].view(torch.int32))[0]) == 0
 
 
+def test_train_autotuner_keeps_the_results(ocd):
+    """ocd_autotune_train picks and caches a plan; the training step under it gives the
+    untuned step's loss and gradients (FP32 rounding apart) and reports it."""
+    B, U, W, S, Q, K = 128, 16, 44, 4, 4, 4
+    wl, N0, lam, beta = _setup("hybrid", B, U, W, S, Q, K, seed=4)
+    H, y, lam_t = dev(wl["H"]), dev(wl["y"]), dev(lam)
+    bits = torch.from_numpy(wl["bits"]).cuda()
+    pb = ocd.problem(B, U, W, S, Q, K, "hybrid", "f32", N0, 1.0, beta)
+    before = ocd.train_step(H, y, bits, K, Q, "hybrid", N0, 1.0, beta, lam=lam_t)
+    ws = torch.zeros(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+    loss, dlam, dbeta = (torch.empty(1, device="cuda"), torch.empty(K, device="cuda"),
+                         torch.empty(1, device="cuda"))
+    dy = torch.empty(W, S, B, dtype=torch.complex64, device="cuda")
+    tuned = ocd.ocd_autotune_train(pb, H, y, lam_t, bits, loss, dlam, dbeta, dy, ws, repeats=1)
+    say("  tuned train plan", tuned.as_dict())
+    assert ocd.ocd_train_plan(pb).as_dict() == tuned.as_dict()
+    after = ocd.train_step(H, y, bits, K, Q, "hybrid", N0, 1.0, beta, lam=lam_t)
+    torch.cuda.synchronize()
+    assert abs(float(host(after[0])[0]) - float(host(before[0])[0])) <= \
+        LOSS_TOL * float(host(before[0])[0])
+    assert rel(host(after[1]), host(before[1])) <= GRAD_TOL
+    assert abs(float(host(after[2])[0]) - float(host(before[2])[0])) <= \
+        GRAD_TOL * abs(float(host(before[2])[0]))
+    assert rel(host(after[3]), host(before[3])) <= GRAD_TOL
+
+
 def test_train_step_rejects_bad_arguments(ocd):
     B, U, W, S, Q, K = 64, 4, 4, 2, 4, 2
     pb = ocd.problem(B, U, W, S, Q, K, "hybrid", "f32", 0.1, 1.0, 0.7)
