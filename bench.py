@@ -549,8 +549,13 @@ def main():
     if plan.channel_in_registers:
         fwd_kernel = "ocd::k_forward_reg<%d, %d, 8, false, false>" % (plan.lanes_per_vector, npl)
     else:
-        uc = U if (U in (8, 16) and npl <= 8) else 0
-        fwd_kernel = "ocd::k_forward<%d, %d, false, false, %d>" % (plan.lanes_per_vector, npl, uc)
+        # the instantiation the launcher picks: unrolled users for U = 8 or 16, their
+        # chunked form for other multiples of 8 (entries per lane <= 8); one-ahead
+        # column reads only with at most two waves per SIMD (not at this size)
+        uc = U if (U in (8, 16) and npl <= 8) else (8 if (U % 8 == 0 and npl <= 8) else 0)
+        chunked = uc == 8 and U != 8
+        fwd_kernel = "ocd::k_forward<%d, %d, false, false, %d, false, %s>" % (
+            plan.lanes_per_vector, npl, uc, "true" if chunked else "false")
     traffic = read_traffic(TRAFFIC_TAG)
     result = {
         "metric": "detected Gb/s & % HBM peak (B=128,U=8,64QAM,K=3); fwd+bwd vectors/s",
