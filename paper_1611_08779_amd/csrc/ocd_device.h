@@ -115,18 +115,29 @@ __device__ __forceinline__ float2 half2_to_float2(uint32_t bits)
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 
+// A caller's device buffer as a global-address-space pointer.  Kernels that read
+// their buffer pointers from memory (the batched kernel's job table) would
+// otherwise address them as generic (FLAT) pointers, whose loads and stores also
+// count against the LDS wait counter: every LDS wait would then wait for the
+// global accesses in flight as well.  Only ever applied to the caller's buffers.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *global_ptr(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Two consecutive complex entries at element e (aligned: e even), FP32 out.
 // No branch: the caller passes an address that is always valid and selects.
 template <bool F16>
 __device__ __forceinline__ float4 load_pair(const void *base, long e)
 {
     if constexpr (!F16) {
-        const f32x4_t q = __builtin_nontemporal_load(
-            reinterpret_cast<const f32x4_t *>(reinterpret_cast<const float2 *>(base) + e));
+        const f32x4_t q = __builtin_nontemporal_load(global_ptr(
+            reinterpret_cast<const f32x4_t *>(reinterpret_cast<const float2 *>(base) + e)));
         return make_float4(q.x, q.y, q.z, q.w);
     } else {
-        const u32x2_t q = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x2_t *>(reinterpret_cast<const uint32_t *>(base) + e));
+        const u32x2_t q = __builtin_nontemporal_load(global_ptr(
+            reinterpret_cast<const u32x2_t *>(reinterpret_cast<const uint32_t *>(base) + e)));
         const float2 a = half2_to_float2(q.x), b = half2_to_float2(q.y);
         return make_float4(a.x, a.y, b.x, b.y);
     }
@@ -142,10 +153,12 @@ template <bool F16>
 __device__ __forceinline__ float4 load_pair_at(const unsigned char *base, unsigned off)
 {
     if constexpr (!F16) {
-        const f32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(base + off));
+        const f32x4_t q =
+            __builtin_nontemporal_load(global_ptr(reinterpret_cast<const f32x4_t *>(base + off)));
         return make_float4(q.x, q.y, q.z, q.w);
     } else {
-        const u32x2_t q = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t *>(base + off));
+        const u32x2_t q =
+            __builtin_nontemporal_load(global_ptr(reinterpret_cast<const u32x2_t *>(base + off)));
         const float2 a = half2_to_float2(q.x), b = half2_to_float2(q.y);
         return make_float4(a.x, a.y, b.x, b.y);
     }
@@ -155,7 +168,7 @@ __device__ __forceinline__ float4 load_pair_at(const unsigned char *base, unsign
 // half pairs), from a workgroup-uniform base plus a 32-bit byte offset.
 __device__ __forceinline__ u32x2_t load_pair_raw16(const unsigned char *base, unsigned off)
 {
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x2_t *>(base + off));
+    return __builtin_nontemporal_load(global_ptr(reinterpret_cast<const u32x2_t *>(base + off)));
 }
 
 // Load `N` consecutive complex entries starting at element `e` of a row,
@@ -168,18 +181,20 @@ __device__ __forceinline__ void load_chunk(const void *base, long e, int b, int 
 {
     if (vec_ok && b + N <= limit) {
         if constexpr (!F16) {
-            const float2 *p = reinterpret_cast<const float2 *>(base) + e;
+            const auto p = global_ptr(reinterpret_cast<const float2 *>(base) + e);
             if constexpr (N == 2) {
-                f32x4_t q = __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(p));
+                f32x4_t q = __builtin_nontemporal_load(
+                    reinterpret_cast<const __attribute__((address_space(1))) f32x4_t *>(p));
                 out[0] = make_float2(q.x, q.y);
                 out[1] = make_float2(q.z, q.w);
             } else {
                 for (int t = 0; t < N; ++t) out[t] = p[t];
             }
         } else {
-            const uint32_t *p = reinterpret_cast<const uint32_t *>(base) + e;
+            const auto p = global_ptr(reinterpret_cast<const uint32_t *>(base) + e);
             if constexpr (N == 2) {
-                u32x2_t q = __builtin_nontemporal_load(reinterpret_cast<const u32x2_t *>(p));
+                u32x2_t q = __builtin_nontemporal_load(
+                    reinterpret_cast<const __attribute__((address_space(1))) u32x2_t *>(p));
                 out[0] = half2_to_float2(q.x);
                 out[1] = half2_to_float2(q.y);
             } else {
@@ -190,8 +205,8 @@ __device__ __forceinline__ void load_chunk(const void *base, long e, int b, int 
     }
     for (int t = 0; t < N; ++t) {
         if (b + t < limit) {
-            if constexpr (!F16) out[t] = reinterpret_cast<const float2 *>(base)[e + t];
-            else out[t] = half2_to_float2(reinterpret_cast<const uint32_t *>(base)[e + t]);
+            if constexpr (!F16) out[t] = global_ptr(reinterpret_cast<const float2 *>(base))[e + t];
+            else out[t] = half2_to_float2(global_ptr(reinterpret_cast<const uint32_t *>(base))[e + t]);
         } else {
             out[t] = make_float2(0.f, 0.f);
         }

@@ -235,8 +235,8 @@ __device__ __forceinline__ float2 llr_coef(const Params &P, float g, float pK, f
 
 // Soft output of one axis of one user: t = the axis of z_u times a, c = the
 // LLR scale (llr_coef); writes the HALF LLRs of that axis, MSB first.
-template <int HALF>
-__device__ __forceinline__ void axis_llrs(float t, float c, float *dst)
+template <int HALF, typename Dst>
+__device__ __forceinline__ void axis_llrs(float t, float c, Dst dst)
 {
     float D[HALF];
     pam_metrics<HALF>(t, D);
@@ -257,17 +257,18 @@ __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, i
     const int Kt = P.per_sweep ? P.K : 1;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
     const int rows = nslots * U;
-    const float lamK = P.lambda ? P.lambda[P.K - 1] : P.lam_default;
+    const float lamK = P.lambda ? global_ptr(P.lambda)[P.K - 1] : P.lam_default;
     if (P.g_in) {
         for (int i = threadIdx.x; i < rows; i += blockDim.x) {
             const int slot = slot_of_row(P, i), u = i - slot * U;
-            const float g = P.g_in[(long)w_first * U + i];
+            const float g = global_ptr(P.g_in)[(long)w_first * U + i];
             sm.g[i] = g;
-            sm.lc[i] = llr_coef(P, g, P.p_in[((long)(w_first + slot) * Kt + Kt - 1) * U + u], lamK);
+            sm.lc[i] = llr_coef(P, g, global_ptr(P.p_in)[((long)(w_first + slot) * Kt + Kt - 1) * U + u],
+                                lamK);
         }
         for (int i = threadIdx.x; i < nslots * Kt * U; i += blockDim.x) {
             const long gi = (long)w_first * Kt * U + i;
-            sm.dp[i] = make_float2(P.dinv_in[gi], P.p_in[gi]);
+            sm.dp[i] = make_float2(global_ptr(P.dinv_in)[gi], global_ptr(P.p_in)[gi]);
         }
         __syncthreads();
         return;
@@ -299,7 +300,7 @@ __device__ void stage_preprocess(const Params &P, const Smem &sm, int w_first, i
             sm.lc[row] = llr_coef(P, acc, di * acc, lamK);
         }
         for (int kt = l16; kt < Kt; kt += 16) {
-            const float lam = P.lambda ? P.lambda[kt] : P.lam_default;
+            const float lam = P.lambda ? global_ptr(P.lambda)[kt] : P.lam_default;
             const float den = acc + lam;
             const float di = den > 0.f ? 1.0f / den : 0.f;
             sm.dp[((size_t)slot * Kt + kt) * U + u] = make_float2(di, di * acc);

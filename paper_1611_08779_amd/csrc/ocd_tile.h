@@ -70,7 +70,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     const float beta = P.beta;
     auto sweep_done = [&](int k) {
         if (P.z_hist && active)
-            for (int u = j; u < U; u += L) P.z_hist[((long)v * P.K + k) * U + u] = zv[u];
+            for (int u = j; u < U; u += L) global_ptr(P.z_hist)[((long)v * P.K + k) * U + u] = zv[u];
     };
     if constexpr (UC > 0 && CHUNKED) {
         constexpr int BP = L * NPL;
@@ -171,18 +171,18 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     if (!active) return;
     // outputs: lanes of the group take users (z) and (user, axis) pairs (LLRs)
     if (P.z) {
-        float2 *zt = P.z + (size_t)tile.vbase * U;   // workgroup-uniform base
+        const auto zt = global_ptr(P.z + (size_t)tile.vbase * U);   // workgroup-uniform base
         for (int u = j; u < U; u += L) zt[grp * U + u] = zv[u];
     }
     if (P.llr) {
         const int Q = P.Q, half = Q >> 1;
-        float *lt = P.llr + (size_t)tile.vbase * U * Q;
+        const auto lt = global_ptr(P.llr + (size_t)tile.vbase * U * Q);
         const float2 *lcs = sm.lc + (size_t)slot * U;
         for (int idx = j; idx < 2 * U; idx += L) {
             const int u = idx >> 1, ax = idx & 1;
             const float2 zu = zv[u], co = lcs[u];
             const float t = (ax ? zu.y : zu.x) * co.x;
-            float *dst = lt + (grp * U + u) * Q + ax * half;
+            const auto dst = lt + (grp * U + u) * Q + ax * half;
             if (half == 3) axis_llrs<3>(t, co.y, dst);
             else if (half == 2) axis_llrs<2>(t, co.y, dst);
             else axis_llrs<1>(t, co.y, dst);

@@ -24,10 +24,12 @@ def f32(x):
     return float(np.float32(x))
 
 
-# uneven shapes drawn like the 48-job batch, cut down so the oracle stays fast
+# uneven shapes drawn like the 48-job batch, cut down so the oracle stays fast; with
+# U = 24 (three chunks of the chunked user loop) at a B that is not a power of two
 JOBS = [
     (64, 4, 21, 2), (128, 8, 30, 3), (256, 32, 5, 4), (128, 16, 11, 2), (64, 32, 9, 3),
     (256, 4, 17, 2), (128, 32, 3, 4), (64, 8, 40, 3), (256, 16, 7, 2), (33, 5, 6, 3),
+    (96, 24, 4, 3), (200, 24, 3, 2),
 ]
 
 

@@ -131,6 +131,7 @@ def test_train_step_matches_the_oracle(ocd, mode):
     (128, 16, 17, 4, 4, 1, "hybrid", "f32"),
     (128, 8, 24, 4, 4, 3, "hybrid", "f16"),
     (200, 12, 9, 7, 6, 3, "mmse", "f32"),
+    (256, 32, 4, 2, 4, 2, "hybrid", "f32"),   # the most users, the largest H_w
 ])
 def test_train_step_edge_shapes(ocd, case):
     B, U, W, S, Q, K, mode, storage = case
