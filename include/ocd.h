@@ -413,6 +413,15 @@ typedef struct {
 ocd_status ocd_ofdm_demodulate(const ocd_ofdm_shape *sh, const float *x, float *y,
                                hipStream_t stream);
 
+/* Measurement support, not part of the detector: launches `blocks` workgroups of
+ * 256 threads, each thread running 8 independent FP32 FMA chains for `iters` x 16
+ * updates, with packed FP32 instruction selection off like every kernel of this
+ * library; *flops receives the launch's flop count (2 per FMA).  Timing it (events
+ * on `stream`) gives the non-packed FP32 FMA rate the detection kernels can reach.
+ *   out     device, >= 256 floats; written only in a case that never occurs
+ * OCD_EINVAL for blocks or iters below 1 or NULL pointers; asynchronous. */
+ocd_status ocd_probe_fma(int blocks, int iters, float *out, double *flops, hipStream_t stream);
+
 /* Drops every cached hipGraph and pinned staging buffer (e.g. before freeing a
  * workspace that ocd_detect_jobs captured). */
 void ocd_release_graphs(void);

@@ -32,7 +32,7 @@ __all__ = [
     "ocd_status_str", "ocd_version", "ocd_preprocess", "ocd_detect",
     "ocd_backward_workspace_bytes", "ocd_detect_backward", "ocd_detect_backward_bce",
     "ocd_detect_backward_bce_noalloc", "ocd_detect_train_bce", "ocd_train_plan",
-    "ocd_autotune_train",
+    "ocd_autotune_train", "ocd_probe_fma",
     "ocd_get_plan", "ocd_set_plan",
     "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
     "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed", "ocd_ofdm_demodulate",
@@ -138,6 +138,8 @@ def _load():
         "ocd_detect_mmse": ([P, vp, vp, fp, fp, ctypes.POINTER(Plan), vp], ctypes.c_int),
         "ocd_detect_fixed": ([P, vp, vp, vp, fp, vp], ctypes.c_int),
         "ocd_ofdm_demodulate": ([ctypes.POINTER(OfdmShape), vp, vp, vp], ctypes.c_int),
+        "ocd_probe_fma": ([ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double), vp],
+                          ctypes.c_int),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -490,6 +492,15 @@ def ocd_jobs_schedule(jobs) -> dict:
     _check("ocd_jobs_schedule", _lib.ocd_jobs_schedule(arr, len(jobs), ctypes.byref(pers),
                                                        ctypes.byref(pol), ctypes.byref(mode)))
     return {"persistent": pers.value, "tile_policy": pol.value, "lane_mode": mode.value}
+
+
+def ocd_probe_fma(blocks, iters, out, stream=None) -> float:
+    """Launches the FP32 FMA-rate probe; returns the launch's flop count."""
+    fl = ctypes.c_double(0.0)
+    _check("ocd_probe_fma", _lib.ocd_probe_fma(int(blocks), int(iters),
+                                               _dev_ptr(out, "out", (torch.float32,), 1024),
+                                               ctypes.byref(fl), _stream(stream)))
+    return fl.value
 
 
 def ocd_release_graphs() -> None:

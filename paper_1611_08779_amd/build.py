@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libocd.so")
 
 SOURCES = ["ocd_api.hip", "ocd_forward.hip", "ocd_forward_reg.hip", "ocd_backward.hip", "ocd_train.hip",
            "ocd_jobs.hip",
-           "ocd_mmse.hip", "ocd_fixed.hip", "ocd_ofdm.hip"]
+           "ocd_mmse.hip", "ocd_fixed.hip", "ocd_ofdm.hip", "ocd_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -126,6 +126,25 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *global_ptr(T *p)
     return (__attribute__((address_space(1))) T *)p;
 }
 
+// One complex FP32 entry of a caller's buffer, loaded or stored through the global
+// address space (as a plain two-float vector: the float2 class type cannot be
+// accessed through an address-space-qualified pointer).
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 global_load2(const float2 *p)
+{
+    const f32x2_t q = *global_ptr(reinterpret_cast<const f32x2_t *>(p));
+    return make_float2(q.x, q.y);
+}
+
+__device__ __forceinline__ void global_store2(float2 *p, float2 v)
+{
+    f32x2_t q;
+    q.x = v.x;
+    q.y = v.y;
+    *global_ptr(reinterpret_cast<f32x2_t *>(p)) = q;
+}
+
 // Two consecutive complex entries at element e (aligned: e even), FP32 out.
 // No branch: the caller passes an address that is always valid and selects.
 template <bool F16>
@@ -181,14 +200,14 @@ __device__ __forceinline__ void load_chunk(const void *base, long e, int b, int 
 {
     if (vec_ok && b + N <= limit) {
         if constexpr (!F16) {
-            const auto p = global_ptr(reinterpret_cast<const float2 *>(base) + e);
+            const float2 *p = reinterpret_cast<const float2 *>(base) + e;
             if constexpr (N == 2) {
-                f32x4_t q = __builtin_nontemporal_load(
-                    reinterpret_cast<const __attribute__((address_space(1))) f32x4_t *>(p));
+                f32x4_t q =
+                    __builtin_nontemporal_load(global_ptr(reinterpret_cast<const f32x4_t *>(p)));
                 out[0] = make_float2(q.x, q.y);
                 out[1] = make_float2(q.z, q.w);
             } else {
-                for (int t = 0; t < N; ++t) out[t] = p[t];
+                for (int t = 0; t < N; ++t) out[t] = global_load2(p + t);
             }
         } else {
             const auto p = global_ptr(reinterpret_cast<const uint32_t *>(base) + e);
@@ -205,7 +224,7 @@ __device__ __forceinline__ void load_chunk(const void *base, long e, int b, int 
     }
     for (int t = 0; t < N; ++t) {
         if (b + t < limit) {
-            if constexpr (!F16) out[t] = global_ptr(reinterpret_cast<const float2 *>(base))[e + t];
+            if constexpr (!F16) out[t] = global_load2(reinterpret_cast<const float2 *>(base) + e + t);
             else out[t] = half2_to_float2(global_ptr(reinterpret_cast<const uint32_t *>(base))[e + t]);
         } else {
             out[t] = make_float2(0.f, 0.f);

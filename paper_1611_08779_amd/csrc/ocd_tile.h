@@ -70,7 +70,7 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     const float beta = P.beta;
     auto sweep_done = [&](int k) {
         if (P.z_hist && active)
-            for (int u = j; u < U; u += L) global_ptr(P.z_hist)[((long)v * P.K + k) * U + u] = zv[u];
+            for (int u = j; u < U; u += L) global_store2(P.z_hist + ((long)v * P.K + k) * U + u, zv[u]);
     };
     if constexpr (UC > 0 && CHUNKED) {
         constexpr int BP = L * NPL;
@@ -171,8 +171,8 @@ __device__ void forward_tile(const Params &P, const Smem &sm, const Tile &tile)
     if (!active) return;
     // outputs: lanes of the group take users (z) and (user, axis) pairs (LLRs)
     if (P.z) {
-        const auto zt = global_ptr(P.z + (size_t)tile.vbase * U);   // workgroup-uniform base
-        for (int u = j; u < U; u += L) zt[grp * U + u] = zv[u];
+        float2 *zt = P.z + (size_t)tile.vbase * U;   // workgroup-uniform base
+        for (int u = j; u < U; u += L) global_store2(zt + grp * U + u, zv[u]);
     }
     if (P.llr) {
         const int Q = P.Q, half = Q >> 1;

@@ -272,3 +272,15 @@ def test_ofdm_shapes_are_checked_on_the_host(lib, bad):
     sh = OfdmShape(**{**good, **bad})
     assert lib.ocd_ofdm_demodulate(ctypes.byref(sh), d, d, None) == -1
     assert lib.ocd_ofdm_demodulate(ctypes.byref(OfdmShape(**good)), None, d, None) == -1
+
+
+def test_fma_probe_checks_its_arguments_on_the_host(lib):
+    lib.ocd_probe_fma.restype = ctypes.c_int
+    lib.ocd_probe_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    d = ctypes.c_void_p(0x1000)
+    fl = ctypes.c_double(0.0)
+    assert lib.ocd_probe_fma(0, 10, d, ctypes.byref(fl), None) == -1
+    assert lib.ocd_probe_fma(10, 0, d, ctypes.byref(fl), None) == -1
+    assert lib.ocd_probe_fma(10, 10, None, ctypes.byref(fl), None) == -1
+    assert lib.ocd_probe_fma(10, 10, d, None, None) == -1
