@@ -229,10 +229,11 @@ ocd_status ocd_detect_backward_bce_noalloc(const ocd_problem *pb, const void *H,
  *                         columns of its H_w in registers and nothing is staged (the
  *                         choice when few do).  1 needs U <= 8 and
  *                         B <= 8 * lanes_per_vector, and is forward-only.
- *   stagger               0..16, LDS-staged plans: workgroup b waits
+ *   stagger               0..16: workgroup b waits
  *                         max(0, b / 128 - 1) * stagger * 512 clocks before it loads
- *                         its tile, so that the workgroups dispatched first get their
- *                         data first and start computing while later ones load
+ *                         its tile (or its columns, channel_in_registers = 1), so
+ *                         that the workgroups dispatched first get their data
+ *                         first and start computing while later ones load
  *                         (0: every workgroup loads at once). */
 typedef struct {
     int lanes_per_vector;
@@ -259,6 +260,17 @@ ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
  * to that JSON file, keyed by GPU architecture and shape. */
 ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,
                         float *z, float *llr, int repeats, ocd_plan *best, hipStream_t stream);
+
+/* The same autotuner over n >= 1 input sets: H and y are host arrays of n device
+ * pointers (each set laid out as for ocd_detect; the arrays are read during the
+ * call only).  Every candidate plan is timed over `repeats` passes through the n
+ * sets in order, so that with more sets than the caches hold each launch reads
+ * its inputs from HBM, as a stream of distinct slots does; ocd_autotune is the
+ * n = 1 case, whose input stays cache-resident between launches and can favour
+ * another plan.  z and llr are overwritten.  EINVAL on n < 1 or a NULL pointer. */
+ocd_status ocd_autotune_inputs(const ocd_problem *pb, int n, const void *const *H,
+                               const void *const *y, float *z, float *llr, int repeats,
+                               ocd_plan *best, hipStream_t stream);
 
 /* Autotuner of the training step: times every valid plan of ocd_detect_train_bce
  * (those whose z history fits in LDS, then the staggered staging on the fastest)

@@ -34,7 +34,8 @@ __all__ = [
     "ocd_detect_backward_bce_noalloc", "ocd_detect_train_bce", "ocd_train_plan",
     "ocd_autotune_train", "ocd_probe_fma",
     "ocd_get_plan", "ocd_set_plan",
-    "ocd_autotune", "ocd_autotune_backward", "ocd_jobs_workspace_bytes", "ocd_detect_jobs",
+    "ocd_autotune", "ocd_autotune_inputs", "ocd_autotune_backward", "ocd_jobs_workspace_bytes",
+    "ocd_detect_jobs",
     "ocd_release_graphs", "ocd_detect_mmse", "ocd_detect_fixed", "ocd_ofdm_demodulate",
     "OfdmShape", "ofdm_demodulate",
     "problem", "detect", "preprocess", "backward", "train_step", "detect_jobs", "detect_mmse", "detect_fixed",
@@ -126,6 +127,8 @@ def _load():
         "ocd_get_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_set_plan": ([P, ctypes.POINTER(Plan)], ctypes.c_int),
         "ocd_autotune": ([P, vp, vp, fp, fp, ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
+        "ocd_autotune_inputs": ([P, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), fp, fp,
+                                 ctypes.c_int, ctypes.POINTER(Plan), vp], ctypes.c_int),
         "ocd_autotune_backward": ([P, vp, vp, fp, fp, fp, fp, fp, fp, vp, sz, ctypes.c_int,
                                    ctypes.POINTER(Plan), vp], ctypes.c_int),
         "ocd_jobs_workspace_bytes": ([P, ctypes.c_int], sz),
@@ -376,6 +379,28 @@ def ocd_autotune(pb: Problem, H, y, z, llr, repeats=5, stream=None) -> Plan:
         _dev_ptr(llr, "llr", (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev),
         int(repeats), ctypes.byref(pl), _stream(stream))
     _check("ocd_autotune", st)
+    return pl
+
+
+def ocd_autotune_inputs(pb: Problem, Hs, ys, z, llr, repeats=2, stream=None) -> Plan:
+    """``ocd_autotune`` over several input sets (sequences of H and y tensors of the
+    problem's shape, one device), each candidate timed over `repeats` passes
+    through all of them."""
+    if len(Hs) != len(ys) or not Hs:
+        raise ValueError("ocd_autotune_inputs: Hs and ys must be non-empty and of equal length")
+    dev = Hs[0].device
+    n = len(Hs)
+    hp = (ctypes.c_void_p * n)(*[_dev_ptr(H, "H", _in_dtypes(pb), pb.W * pb.U * pb.B * _cbytes(pb), dev)
+                                 for H in Hs])
+    yp = (ctypes.c_void_p * n)(*[_dev_ptr(y, "y", _in_dtypes(pb), pb.W * pb.S * pb.B * _cbytes(pb), dev)
+                                 for y in ys])
+    pl = Plan()
+    st = _lib.ocd_autotune_inputs(
+        ctypes.byref(pb), n, hp, yp,
+        _dev_ptr(z, "z", (torch.complex64, torch.float32), pb.W * pb.S * pb.U * 8, dev),
+        _dev_ptr(llr, "llr", (torch.float32,), pb.W * pb.S * pb.U * pb.Q * 4, dev),
+        int(repeats), ctypes.byref(pl), _stream(stream))
+    _check("ocd_autotune_inputs", st)
     return pl
 
 

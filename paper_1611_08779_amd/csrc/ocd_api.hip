@@ -526,12 +526,18 @@ extern "C" ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan)
     return OCD_OK;
 }
 
-extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y, float *z,
-                                   float *llr, int repeats, ocd_plan *best, hipStream_t stream)
+// The forward autotuner over n input sets: each candidate is timed over `repeats`
+// passes through all n sets (H[i], y[i]), so that with more sets than the caches
+// hold every launch reads its inputs from HBM, as a stream of distinct slots does.
+static ocd_status autotune_forward(const ocd_problem *pb, int n, const void *const *H,
+                                   const void *const *y, float *z, float *llr, int repeats,
+                                   ocd_plan *best, hipStream_t stream)
 {
     ocd_status st = validate(pb);
     if (st != OCD_OK) return st;
-    if (!H || !y || !z || !llr || !best) return OCD_EINVAL;
+    if (n < 1 || !H || !y || !z || !llr || !best) return OCD_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!H[i] || !y[i]) return OCD_EINVAL;
     if (pb->W == 0) {
         *best = heuristic_plan(pb, nullptr, false, true);
         return OCD_OK;
@@ -571,28 +577,30 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
     float best_ms = 1e30f;
     ocd_plan best_pl = cands[0];
     st = OCD_OK;
+    const int launches = repeats * n;
+    auto launch = [&](const ocd_plan &pl, int i) {
+        return run_forward(pb, pl, H[i % n], y[i % n], nullptr, nullptr, nullptr, nullptr, z, llr,
+                           nullptr, stream);
+    };
     for (const ocd_plan &pl : cands) {
-        st = run_forward(pb, pl, H, y, nullptr, nullptr, nullptr, nullptr, z, llr, nullptr, stream);
+        st = launch(pl, n - 1);
         if (st != OCD_OK) break;
         (void)hipEventRecord(e0, stream);
-        for (int i = 0; i < repeats && st == OCD_OK; ++i)
-            st = run_forward(pb, pl, H, y, nullptr, nullptr, nullptr, nullptr, z, llr, nullptr, stream);
+        for (int i = 0; i < launches && st == OCD_OK; ++i) st = launch(pl, i);
         (void)hipEventRecord(e1, stream);
         if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) { st = OCD_EDEVICE; break; }
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best_ms) { best_ms = ms; best_pl = pl; }
     }
-    // second stage: the staggered staging on the fastest LDS-staged plan
-    if (st == OCD_OK && !best_pl.channel_in_registers) {
+    // second stage: staggered starts on the fastest plan
+    if (st == OCD_OK) {
         const ocd_plan base = best_pl;
         for (int sg : {1, 2, 4}) {
             ocd_plan pl = base;
             pl.stagger = sg;
             (void)hipEventRecord(e0, stream);
-            for (int i = 0; i < repeats && st == OCD_OK; ++i)
-                st = run_forward(pb, pl, H, y, nullptr, nullptr, nullptr, nullptr, z, llr,
-                                 nullptr, stream);
+            for (int i = 0; i < launches && st == OCD_OK; ++i) st = launch(pl, i);
             (void)hipEventRecord(e1, stream);
             if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) { st = OCD_EDEVICE; break; }
             float ms = 0.f;
@@ -609,6 +617,19 @@ extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const v
     store_plan(plan_key(pb, true, false), best_pl, true);
     *best = best_pl;
     return OCD_OK;
+}
+
+extern "C" ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y, float *z,
+                                   float *llr, int repeats, ocd_plan *best, hipStream_t stream)
+{
+    return autotune_forward(pb, 1, &H, &y, z, llr, repeats, best, stream);
+}
+
+extern "C" ocd_status ocd_autotune_inputs(const ocd_problem *pb, int n, const void *const *H,
+                                          const void *const *y, float *z, float *llr, int repeats,
+                                          ocd_plan *best, hipStream_t stream)
+{
+    return autotune_forward(pb, n, H, y, z, llr, repeats, best, stream);
 }
 
 // ------------------------------------------------------------------ adjoint

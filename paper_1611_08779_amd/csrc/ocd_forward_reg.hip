@@ -8,7 +8,10 @@
 // order the first sweep consumes them, and does the preprocessing of user u just
 // before that user's first update, so the early updates of the first sweep
 // overlap the round trip of the later columns.  The user count has a compile-time
-// bound UC (U <= UC = 8); z, d^-1, p and g live in registers as well.
+// bound UC (U <= UC = 8); z, d^-1, p and g live in registers as well.  With every
+// workgroup resident at once, all of them would wait for their loads together and
+// then compute together; the plan's stagger delays later workgroups
+// (stagger_loads) so that earlier ones compute while later ones load.
 #include <type_traits>
 
 #include "ocd_stage.h"
@@ -212,28 +215,35 @@ __global__ __launch_bounds__(256) void k_forward_reg(Params P)
     const int vb = (int)blockIdx.x * P.vpb;
     const bool active = grp < min(P.vpb, P.W * P.S - vb);
     __shared__ UserRow<UC> rows[256 / L];
+    stagger_loads(P);
     RegVec<NPL, UC, F16> x;
     reg_load<L, NPL, UC>(P, vb, grp, j, active, x);
     reg_compute<L, NPL, UC, F16, BOX>(P, vb, grp, j, active, x, rows[grp]);
 }
 
 template <int L, int NPL, int UC, bool F16, bool BOX>
-static void launch_reg_k(const Params &p, int threads, hipStream_t s)
+static hipError_t launch_reg_k(const Params &p, int threads, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_forward_reg<L, NPL, UC, F16, BOX>), dim3(p.nblocks), dim3(threads), 0, s, p);
+    auto fn = k_forward_reg<L, NPL, UC, F16, BOX>;
+    Params q = p;
+    if (q.stagger > 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(fn), threads, 0);
+        if (e != hipSuccess) return e;
+        q.stagger_cap = per_cu * device_cu_count();
+    }
+    hipLaunchKernelGGL(fn, dim3(q.nblocks), dim3(threads), 0, s, q);
+    return hipGetLastError();
 }
 
 template <int L, int NPL, int UC>
 static hipError_t launch_reg_t(bool f16, const Params &p, int threads, hipStream_t s)
 {
-    if (f16) {
-        if (p.box) launch_reg_k<L, NPL, UC, true, true>(p, threads, s);
-        else launch_reg_k<L, NPL, UC, true, false>(p, threads, s);
-    } else {
-        if (p.box) launch_reg_k<L, NPL, UC, false, true>(p, threads, s);
-        else launch_reg_k<L, NPL, UC, false, false>(p, threads, s);
-    }
-    return hipGetLastError();
+    if (f16) return p.box ? launch_reg_k<L, NPL, UC, true, true>(p, threads, s)
+                          : launch_reg_k<L, NPL, UC, true, false>(p, threads, s);
+    return p.box ? launch_reg_k<L, NPL, UC, false, true>(p, threads, s)
+                 : launch_reg_k<L, NPL, UC, false, false>(p, threads, s);
 }
 
 template <int L>

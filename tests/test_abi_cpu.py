@@ -137,7 +137,7 @@ def test_backward_autotune_rejects_bad_arguments(lib):
                                           [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
                                            ctypes.c_void_p, ctypes.c_void_p])
     d = ctypes.c_void_p(0x1000)
-    best = ctypes.create_string_buffer(16)
+    best = ctypes.create_string_buffer(64)
     # no place for the plan
     assert lib.ocd_autotune_backward(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, n, 1, None,
                                      None) == -1
@@ -147,6 +147,23 @@ def test_backward_autotune_rejects_bad_arguments(lib):
     # workspace too small
     assert lib.ocd_autotune_backward(ctypes.byref(pb), d, d, None, d, d, d, d, d, d, 16, 1, best,
                                      None) == -1
+
+
+def test_multi_input_autotune_rejects_bad_arguments(lib):
+    pb = Problem(**_good())
+    f = lib.ocd_autotune_inputs
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.POINTER(Problem), ctypes.c_int] + [ctypes.c_void_p] * 4 + [
+        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    d = 0x1000
+    two = (ctypes.c_void_p * 2)(d, d)
+    hole = (ctypes.c_void_p * 2)(d, None)
+    best = ctypes.create_string_buffer(64)
+    assert f(ctypes.byref(pb), 0, two, two, d, d, 1, best, None) == -1      # no input set
+    assert f(ctypes.byref(pb), 2, two, hole, d, d, 1, best, None) == -1     # a NULL y
+    assert f(ctypes.byref(pb), 2, None, two, d, d, 1, best, None) == -1     # no H array
+    assert f(ctypes.byref(pb), 2, two, two, d, None, 1, best, None) == -1   # no llr
+    assert f(ctypes.byref(pb), 2, two, two, d, d, 1, None, None) == -1      # no place for the plan
 
 
 def test_jobs_rejects_null_arguments(lib):

@@ -116,46 +116,53 @@ def _full_slot_against_oracle(ocd, pb, wl, want_plan=None):
     return used
 
 
-@pytest.mark.parametrize("stagger", [0, 2])
-def test_b128_u8_64qam_full_slot_bench_plan_forced(ocd, stagger):
+@pytest.mark.parametrize("plan", [(16, 14, 1, 0, 0), (16, 14, 1, 0, 2), (16, 16, 1, 0, 0),
+                                  (16, 16, 1, 0, 2)])
+def test_b128_u8_64qam_full_slot_bench_plan_forced(ocd, plan):
     """The headline slot whole (16,800 vectors) under the launch plans the benchmark's
-    autotuner picks on MI355X: 16 lanes per vector (8 complex entries per lane), one
-    subcarrier's 14 symbols per workgroup (the dense one-subcarrier staging path),
-    XCD-aware tile order, with and without staggered staging; U = 8 takes the
-    unrolled user loop.  That is the kernel instance k_forward<L=16, NPL=8, FP32,
-    MMSE, U=8>, checked against the oracle."""
+    autotuner picks between on MI355X: 16 lanes per vector (8 complex entries per
+    lane), XCD-aware tile order, with and without staggered staging, and either one
+    subcarrier's 14 symbols per workgroup (the dense one-subcarrier staging path) or
+    16 vectors per workgroup (tiles across two subcarriers, the general staging
+    path); U = 8 takes the unrolled user loop.  That is the kernel instance
+    k_forward<L=16, NPL=8, FP32, MMSE, U=8>, checked against the oracle."""
     B, U, W, S, Q, K = 128, 8, 1200, 14, 6, 3
-    say("case headline slot, bench plan (16, 14, 1, 0, %d)" % stagger)
+    say("case headline slot, bench plan %s" % (plan,))
     wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[2, 0, 1])
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", f32(wl["N0"]))
-    ocd.ocd_set_plan(pb, ocd.Plan(16, 14, 1, 0, stagger))
-    _full_slot_against_oracle(ocd, pb, wl, want_plan=(16, 14, 1, 0, stagger))
+    ocd.ocd_set_plan(pb, ocd.Plan(*plan))
+    _full_slot_against_oracle(ocd, pb, wl, want_plan=plan)
 
 
 def test_b128_u8_64qam_full_slot_bench_autotuned(ocd):
-    """The headline slot whole under whatever plan the autotuner chooses, tuned exactly
-    as the benchmark tunes it (ocd_autotune on the slot, 5 repeats); the plan used is
-    the one the tuner returned."""
+    """The headline slot whole under whatever plan the autotuner chooses, tuned the way
+    the benchmark tunes it (ocd_autotune_inputs over a stream of distinct slots, more
+    than the caches hold, 2 passes); the plan used is the one the tuner returned."""
     B, U, W, S, Q, K = 128, 8, 1200, 14, 6, 3
-    say("case headline slot, autotuned plan")
+    say("case headline slot, autotuned plan over 12 slots")
     wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[2, 0, 2])
     N0 = f32(wl["N0"])
     pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
-    H, y = dev(wl["H"]), dev(wl["y"])
+    others = [synth.make_workload_device(B, U, W, S, Q, 20.0, seed=3000 + i, device="cuda")
+              for i in range(11)]
+    Hs = [dev(wl["H"])] + [o["H"] for o in others]
+    ys = [dev(wl["y"])] + [o["y"] for o in others]
     z = torch.empty(W, S, U, dtype=torch.complex64, device="cuda")
     L = torch.empty(W, S, U, Q, dtype=torch.float32, device="cuda")
-    tuned = ocd.ocd_autotune(pb, H, y, z, L, repeats=5)
+    tuned = ocd.ocd_autotune_inputs(pb, Hs, ys, z, L, repeats=2)
     say("  autotuned %s" % tuned.as_dict())
+    del others, Hs, ys
     _full_slot_against_oracle(ocd, pb, wl, want_plan=(
         tuned.lanes_per_vector, tuned.vectors_per_block, tuned.xcd_remap,
         tuned.channel_in_registers, tuned.stagger))
 
 
-@pytest.mark.parametrize("plan", [(16, 4, 0, 1), (32, 4, 0, 1)])
+@pytest.mark.parametrize("plan", [(16, 4, 0, 1), (32, 4, 0, 1), (16, 4, 0, 1, 1)])
 def test_b128_u8_64qam_one_h_per_vector_full_size(ocd, plan):
     """The S = 1 shape the benchmark times, whole: 16,800 vectors with one channel
-    matrix each (B=128, U=8, 64-QAM, K=3, 20 dB), under the two register plans its
-    autotuner chooses between, against the oracle."""
+    matrix each (B=128, U=8, 64-QAM, K=3, 20 dB), under the register plans its
+    autotuner chooses between (with and without staggered starts), against the
+    oracle."""
     run_and_compare(ocd, 128, 8, 16800, 1, 6, 3, "mmse", 20.0, [2, 5, 0], plan=plan)
 
 
@@ -213,6 +220,7 @@ REG_CASES = [
     (33, 4, 20, 1, 4, 2, "mmse", (16, 7, 0, 1)),      # odd B: scalar loads
     (32, 8, 64, 1, 4, 3, "mmse", (16, 16, 0, 1)),     # NPL = 2
     (256, 1, 12, 1, 6, 5, "box", (32, 2, 0, 1)),      # one user, NPL = 8 at L = 32
+    (128, 8, 700, 1, 6, 3, "mmse", (16, 4, 0, 1, 2)),  # staggered starts, 175 workgroups
 ]
 
 
@@ -242,7 +250,8 @@ def test_channel_in_registers_hybrid_and_preprocessed(ocd):
     assert llr_rel_err(host(L2), Lo) <= LLR_TOL_F32
 
 
-@pytest.mark.parametrize("plan", [(32, 8, 0, 1), (16, 16, 0, 1), (16, 5, 0, 1), (32, 2, 0, 1)])
+@pytest.mark.parametrize("plan", [(32, 8, 0, 1), (16, 16, 0, 1), (16, 5, 0, 1), (32, 2, 0, 1),
+                                  (16, 4, 0, 1, 1)])
 def test_channel_in_registers_fp16(ocd, plan):
     """FP16 storage kept packed in registers (mixed-precision FMAs): the same values as
     the oracle on the FP16-rounded inputs, within the FP32 tolerance."""
@@ -409,6 +418,29 @@ def test_fp16_ber_matches_fp32_on_paired_noise(ocd):
 
 
 # ---------------------------------------------------------------- autotuner
+
+def test_autotune_over_several_inputs(ocd):
+    """ocd_autotune_inputs: the plan it returns is valid and cached for the shape, and
+    under it every input set it was timed on is detected as the oracle detects it."""
+    B, U, W, S, Q, K = 64, 8, 40, 14, 4, 3
+    wls = [synth.make_workload(B, U, W, S, Q, 12.0, seed=[11, 1, i]) for i in range(3)]
+    N0 = f32(wls[0]["N0"])
+    pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", N0)
+    Hs, ys = [dev(w["H"]) for w in wls], [dev(w["y"]) for w in wls]
+    z = torch.empty(W, S, U, dtype=torch.complex64, device="cuda")
+    L = torch.empty(W, S, U, Q, dtype=torch.float32, device="cuda")
+    plan = ocd.ocd_autotune_inputs(pb, Hs, ys, z, L, repeats=2)
+    say("  tuned plan", plan.as_dict())
+    assert ocd.ocd_get_plan(pb).as_dict() == plan.as_dict()
+    for w, H, y in zip(wls, Hs, ys):
+        z2, L2, _ = ocd.detect(H, y, K, Q, "mmse", N0)
+        torch.cuda.synchronize()
+        zo, Lo, _ = oracle_ref(w["H"], w["y"], K, Q, "mmse", N0)
+        assert z_rel_err(host(z2), zo) <= Z_TOL_F32
+        assert llr_rel_err(host(L2), Lo) <= LLR_TOL_F32
+    with pytest.raises(ValueError):
+        ocd.ocd_autotune_inputs(pb, [], [], z, L)
+
 
 def test_autotune_returns_a_valid_plan(ocd):
     B, U, W, S, Q, K = 32, 8, 64, 1, 4, 3
