@@ -84,9 +84,17 @@ def source_hash():
 TRAFFIC_TAG = "ocd_forward_b128_u8_w1200_s14_64qam_k3"
 
 
-def read_traffic(kernel_tag):
-    """Measured HBM bytes per launch from a committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources; else None."""
+def plan_fields(plan):
+    """The fields of a launch plan that decide which bytes a launch moves (the
+    stagger only delays workgroup starts)."""
+    return [int(plan["lanes_per_vector"]), int(plan["vectors_per_block"]), int(plan["xcd_remap"]),
+            int(plan["channel_in_registers"])]
+
+
+def read_traffic(kernel_tag, plan):
+    """Measured HBM bytes per launch from a committed rocprofv3 counter summary
+    (one record per profiled plan), if one was taken under this plan on the
+    current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_tag)
     if not os.path.exists(path):
         return None
@@ -94,9 +102,10 @@ def read_traffic(kernel_tag):
         d = json.load(open(path))
     except ValueError:
         return None
-    if d.get("source_hash") != source_hash():
-        return None
-    return d.get("bytes_per_launch")
+    for rec in d.get("records", []):
+        if rec.get("source_hash") == source_hash() and rec.get("plan") == plan_fields(plan):
+            return rec.get("bytes_per_launch")
+    return None
 
 
 class GraphedSteps:
@@ -291,7 +300,7 @@ def _kernel_key(row):
     return name, grid, wg
 
 
-def summarize_profile(dirs, traffic_out, command):
+def summarize_profile(dirs, traffic_out, command, plan=None):
     """Prints the rocprofv3 --stats table and a per-(kernel, grid, workgroup) breakdown
     of the kernel trace; on --pmc FETCH_SIZE / WRITE_SIZE directories prints the
     per-dispatch counters, scales them by what the same counters read for the
@@ -374,8 +383,13 @@ def summarize_profile(dirs, traffic_out, command):
             return 1
         f = max(traffic["FETCH_SIZE"])
         w = max(traffic["WRITE_SIZE"])
+        if plan is None:
+            print("--traffic-out needs the profiled plan (--plan L,VPB,XCD[,STAGGER])",
+                  file=sys.stderr)
+            return 1
         rec = {
             "kernel": f[1], "grid": f[2], "workgroup": f[3],
+            "plan": plan_fields(plan),
             "workload": "B=128 U=8, 1200 subcarriers x 14 symbols, 64-QAM, K=3, MMSE, FP32",
             "fetch_kib_per_launch": f[4], "fetch_scale": f[5],
             "write_kib_per_launch": w[4], "write_scale": w[5],
@@ -383,8 +397,21 @@ def summarize_profile(dirs, traffic_out, command):
             "source_hash": source_hash(),
             "command": command,
         }
+        # one record per profiled plan: a record of the same plan is replaced
+        recs = []
+        if os.path.exists(traffic_out):
+            try:
+                recs = json.load(open(traffic_out)).get("records", [])
+            except (ValueError, AttributeError):
+                recs = []
+        recs = [r for r in recs if r.get("plan") != rec["plan"]] + [rec]
+        doc = {"about": "HBM bytes per launch of the detection kernel from rocprofv3 FETCH_SIZE and "
+                        "WRITE_SIZE, one record per profiled plan (lanes per vector, vectors per "
+                        "workgroup, XCD remap, channel in registers); bench.py reports a record as "
+                        "roofline.traffic when the timed plan and the kernel sources' hash match it",
+               "records": sorted(recs, key=lambda r: r["plan"])}
         with open(traffic_out, "w") as fh:
-            json.dump(rec, fh, indent=1)
+            json.dump(doc, fh, indent=1)
         print("wrote %s: %.3f MB per launch" % (traffic_out, rec["bytes_per_launch"] / 1e6))
     return 0
 
@@ -427,7 +454,12 @@ def main():
     ap.add_argument("--command", default="", help="with --summarize-profile: the profiled command")
     args = ap.parse_args()
     if args.summarize_profile:
-        sys.exit(summarize_profile(args.summarize_profile, args.traffic_out, args.command))
+        pl = None
+        if args.plan:
+            f = [int(x) for x in args.plan.split(",")] + [0, 0]
+            pl = {"lanes_per_vector": f[0], "vectors_per_block": f[1], "xcd_remap": f[2],
+                  "channel_in_registers": 0}
+        sys.exit(summarize_profile(args.summarize_profile, args.traffic_out, args.command, pl))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (subcarriers would be "
@@ -507,7 +539,7 @@ def main():
         # timed over every slot in turn: the steady state the bench measures, inputs
         # read from HBM (one slot alone would stay cache-resident between launches)
         plan = ocd.ocd_autotune_inputs(pb, [s["H"] for s in slots], [s["y"] for s in slots],
-                                       outs[0][0], outs[0][1], repeats=2)
+                                       outs[0][0], outs[0][1], repeats=4)
         log("autotuned plan %s" % plan.as_dict())
 
     def step_fn(i, prob=pb, ins=slots, o=outs):
@@ -561,7 +593,7 @@ def main():
         chunked = uc == 8 and U != 8
         fwd_kernel = "ocd::k_forward<%d, %d, false, false, %d, false, %s>" % (
             plan.lanes_per_vector, npl, uc, "true" if chunked else "false")
-    traffic = read_traffic(TRAFFIC_TAG)
+    traffic = read_traffic(TRAFFIC_TAG, plan.as_dict())
     result = {
         "metric": "detected Gb/s & % HBM peak (B=128,U=8,64QAM,K=3); fwd+bwd vectors/s",
         "value": value,

@@ -78,14 +78,29 @@ def test_summarize_profile_scales_counters_by_the_calibration_copy(tmp_path, cap
     assert "k_forward<16, 8, false, false, 8>" in out
     assert "22.000" in out and "21.000" in out            # avg (stats), mean of the trace
     rec_path = tmp_path / "traffic.json"
-    assert bench.summarize_profile([str(fd), str(wd)], str(rec_path), "cmd") == 0
+    plan_a = {"lanes_per_vector": 16, "vectors_per_block": 14, "xcd_remap": 1,
+              "channel_in_registers": 0}
+    plan_b = dict(plan_a, vectors_per_block=16)
+    # a traffic record names the plan it was taken under
+    assert bench.summarize_profile([str(fd), str(wd)], str(rec_path), "cmd") == 1
+    capsys.readouterr()
+    assert bench.summarize_profile([str(fd), str(wd)], str(rec_path), "cmd", plan_a) == 0
     out = capsys.readouterr().out
     assert "scale 2.0000" in out and "scale 1.0000" in out
-    rec = json.loads(rec_path.read_text())
+    recs = json.loads(rec_path.read_text())["records"]
+    assert len(recs) == 1
+    rec = recs[0]
+    assert rec["plan"] == [16, 14, 1, 0]
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
     assert rec["fetch_kib_per_launch"] == 15100.0          # the median dispatch
     assert rec["bytes_per_launch"] == pytest.approx(15100.0 * 1024 * 2 + 4200.0 * 1024)
     assert rec["source_hash"] == bench.source_hash() and rec["command"] == "cmd"
+    # a second plan adds a record; the same plan again replaces its own
+    assert bench.summarize_profile([str(fd), str(wd)], str(rec_path), "cmd2", plan_b) == 0
+    assert bench.summarize_profile([str(fd), str(wd)], str(rec_path), "cmd3", plan_a) == 0
+    recs = json.loads(rec_path.read_text())["records"]
+    assert [r["plan"] for r in recs] == [[16, 14, 1, 0], [16, 16, 1, 0]]
+    assert [r["command"] for r in recs] == ["cmd3", "cmd2"]
 
 
 def test_summarize_profile_needs_both_counters(tmp_path):
@@ -98,18 +113,28 @@ def test_summarize_profile_needs_both_counters(tmp_path):
     assert bench.summarize_profile([str(fd)], str(tmp_path / "t.json"), "") == 1
 
 
-def test_traffic_record_is_used_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
+def test_traffic_record_is_used_only_for_the_sources_and_plan_it_was_taken_on(tmp_path,
+                                                                              monkeypatch):
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "source_hash", lambda: "abc")
     path = tmp_path / "profiles" / "traffic_tag.json"
-    assert bench.read_traffic("tag") is None                 # no record
-    path.write_text(json.dumps({"source_hash": "abc", "bytes_per_launch": 123.0}))
-    assert bench.read_traffic("tag") == 123.0
-    path.write_text(json.dumps({"source_hash": "old", "bytes_per_launch": 123.0}))
-    assert bench.read_traffic("tag") is None                 # other sources: not this kernel
+    p14 = {"lanes_per_vector": 16, "vectors_per_block": 14, "xcd_remap": 1,
+           "channel_in_registers": 0, "stagger": 2}
+    p16 = dict(p14, vectors_per_block=16)
+    assert bench.read_traffic("tag", p14) is None            # no record
+    rec = {"source_hash": "abc", "plan": [16, 14, 1, 0], "bytes_per_launch": 123.0}
+    path.write_text(json.dumps({"records": [rec]}))
+    assert bench.read_traffic("tag", p14) == 123.0
+    assert bench.read_traffic("tag", dict(p14, stagger=0)) == 123.0   # stagger moves no bytes
+    assert bench.read_traffic("tag", p16) is None            # another plan: other bytes
+    path.write_text(json.dumps({"records": [rec, dict(rec, plan=[16, 16, 1, 0],
+                                                      bytes_per_launch=456.0)]}))
+    assert bench.read_traffic("tag", p16) == 456.0
+    path.write_text(json.dumps({"records": [dict(rec, source_hash="old")]}))
+    assert bench.read_traffic("tag", p14) is None            # other sources: not this kernel
     path.write_text("not json")
-    assert bench.read_traffic("tag") is None
+    assert bench.read_traffic("tag", p14) is None
 
 
 def test_source_hash_covers_the_detection_kernel_sources():
