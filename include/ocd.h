@@ -261,13 +261,14 @@ ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
 ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,
                         float *z, float *llr, int repeats, ocd_plan *best, hipStream_t stream);
 
-/* The same autotuner over n >= 1 input sets: H and y are host arrays of n device
+/* The same autotuner over 1 <= n <= 65536 input sets: H and y are host arrays of n device
  * pointers (each set laid out as for ocd_detect; the arrays are read during the
  * call only).  Every candidate plan is timed over `repeats` passes through the n
  * sets in order, so that with more sets than the caches hold each launch reads
  * its inputs from HBM, as a stream of distinct slots does; ocd_autotune is the
  * n = 1 case, whose input stays cache-resident between launches and can favour
- * another plan.  z and llr are overwritten.  EINVAL on n < 1 or a NULL pointer. */
+ * another plan.  z and llr are overwritten.  EINVAL on n outside that range or a NULL
+ * pointer. */
 ocd_status ocd_autotune_inputs(const ocd_problem *pb, int n, const void *const *H,
                                const void *const *y, float *z, float *llr, int repeats,
                                ocd_plan *best, hipStream_t stream);

@@ -535,7 +535,7 @@ static ocd_status autotune_forward(const ocd_problem *pb, int n, const void *con
 {
     ocd_status st = validate(pb);
     if (st != OCD_OK) return st;
-    if (n < 1 || !H || !y || !z || !llr || !best) return OCD_EINVAL;
+    if (n < 1 || n > 65536 || !H || !y || !z || !llr || !best) return OCD_EINVAL;
     for (int i = 0; i < n; ++i)
         if (!H[i] || !y[i]) return OCD_EINVAL;
     if (pb->W == 0) {

@@ -160,6 +160,7 @@ def test_multi_input_autotune_rejects_bad_arguments(lib):
     hole = (ctypes.c_void_p * 2)(d, None)
     best = ctypes.create_string_buffer(64)
     assert f(ctypes.byref(pb), 0, two, two, d, d, 1, best, None) == -1      # no input set
+    assert f(ctypes.byref(pb), 65537, two, two, d, d, 1, best, None) == -1  # too many sets
     assert f(ctypes.byref(pb), 2, two, hole, d, d, 1, best, None) == -1     # a NULL y
     assert f(ctypes.byref(pb), 2, None, two, d, d, 1, best, None) == -1     # no H array
     assert f(ctypes.byref(pb), 2, two, two, d, None, 1, best, None) == -1   # no llr
