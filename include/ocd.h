@@ -319,7 +319,8 @@ ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const voi
  * Lane modes (complex entries per lane, NPL; a job's lanes per vector are B / NPL):
  *   0: NPL = 8 for every job;  1: NPL = 16 for jobs with B > 128, else 8;
  *   2: as 1, and NPL = 4 for jobs with 32 < B <= 128.
- * A job whose (lanes, NPL) pair the kernel is not built for keeps NPL = 8.
+ * A job whose (lanes, NPL) pair the kernel is not built for keeps NPL = 8; a job
+ * with B <= 16 runs at 4 lanes of 8 entries, the antennas past B zero-padded.
  * When the tables change, the call enqueues a host-to-device copy of them from
  * pinned memory held by the library and first waits for the previous copy from
  * the same workspace, so it may block until earlier work on `stream` consumed

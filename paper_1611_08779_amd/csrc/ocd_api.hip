@@ -140,12 +140,13 @@ static int reg_user_bound(int U, int npl)
 }
 
 bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda, bool backward,
-                 Params &P, int &npl, int &threads, size_t &lds)
+                 Params &P, int &npl, int &threads, size_t &lds, int min_npl)
 {
     const int L = pl.lanes_per_vector;
     if (L != 4 && L != 8 && L != 16 && L != 32) return false;
     npl = npl_for(pb->B, L);
     if (!npl) return false;
+    if (npl < min_npl) npl = min_npl;   // more zero-padded entries per lane than B needs
     if (pl.channel_in_registers < 0 || pl.channel_in_registers > 1) return false;
     if (pl.stagger < 0 || pl.stagger > 16) return false;
     const bool reg = pl.channel_in_registers != 0;

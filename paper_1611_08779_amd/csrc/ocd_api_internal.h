@@ -14,8 +14,10 @@ const char *arch_name();
 int lds_limit_bytes();
 float box_edge(int Q);
 int npl_for(int B, int L);
+// min_npl (a power of two <= 32, or 0): at least this many complex entries per lane,
+// the antennas past B zero-padded (the batched kernel is built for a few widths only)
 bool make_params(const ocd_problem *pb, const ocd_plan &pl, const float *lambda, bool backward,
-                 Params &P, int &npl, int &threads, size_t &lds);
+                 Params &P, int &npl, int &threads, size_t &lds, int min_npl = 0);
 void set_vec_ok(Params &P, const ocd_problem *pb, const void *H, const void *y);
 ocd_plan heuristic_plan(const ocd_problem *pb, const float *lambda, bool backward, bool allow_reg);
 ocd_plan choose_plan(const ocd_problem *pb, const float *lambda, bool backward);

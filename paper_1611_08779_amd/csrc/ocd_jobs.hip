@@ -213,7 +213,9 @@ static ocd_status plan_jobs(const ocd_problem *jobs, int n, int policy, int lane
         // keep two tiles per CU: at most half of the LDS (whole subcarriers first)
         const size_t budget = (size_t)lds_limit_bytes() / 2 - 64;
         while (pl.vectors_per_block >= 1) {
-            if (make_params(pb, pl, nullptr, false, P, npl, threads, lds) && npl == npl_t &&
+            // a job with B <= 16 would take fewer than 8 entries per lane even at 4
+            // lanes; it runs at the built width of 8, zero-padded
+            if (make_params(pb, pl, nullptr, false, P, npl, threads, lds, npl_t) && npl == npl_t &&
                 lds_bytes(P, JOB_THREADS / L, false) <= budget) {
                 lds = lds_bytes(P, JOB_THREADS / L, false);
                 ok = true;

@@ -177,6 +177,18 @@ def test_jobs_rejects_null_arguments(lib):
     assert lib.ocd_detect_jobs(ctypes.byref(pb), None, None, None, None, 0, None, 0, 0, None) == -1
 
 
+def test_jobs_accept_small_antenna_counts(lib):
+    """Jobs with B <= 16 (fewer than 8 entries per lane even at 4 lanes) run at the
+    batched kernel's built width, zero-padded: the planner accepts them beside large
+    ones (the workspace query is host-only)."""
+    lib.ocd_jobs_workspace_bytes.restype = ctypes.c_size_t
+    lib.ocd_jobs_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.c_int]
+    for B in list(range(1, 17)) + [17, 33]:
+        jobs = (Problem * 2)(Problem(**dict(_good(), B=B, U=max(1, min(32, B // 2)))),
+                             Problem(**dict(_good(), B=256, U=8)))
+        assert lib.ocd_jobs_workspace_bytes(jobs, 2) > 0, B
+
+
 class Plan(ctypes.Structure):
     _fields_ = [("lanes_per_vector", ctypes.c_int), ("vectors_per_block", ctypes.c_int),
                 ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int),

@@ -120,6 +120,23 @@ def test_jobs_schedule_reports_the_tuned_choice(ocd):
     assert after["lane_mode"] in (0, 1, 2)
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_jobs_small_antenna_counts(ocd, mode):
+    """Jobs with B <= 16 have fewer antennas than 4 lanes of 8 entries: they run at
+    that width with the antennas past B zero-padded, beside larger jobs, in every lane
+    mode; each against the oracle."""
+    jobs = [(1, 1, 9, 2), (4, 2, 10, 2), (6, 3, 7, 3), (13, 6, 5, 4), (16, 8, 6, 2),
+            (128, 8, 6, 3)]
+    probs, Hs, ys, wls = _make(ocd, jobs=jobs)
+    say("jobs: small antenna counts, lane mode %d" % mode)
+    z, L, ws = ocd.detect_jobs(probs, Hs, ys, flags=ocd.OCD_JOBS_LANE_MODE(mode))
+    torch.cuda.synchronize()
+    for j, (pb, wl) in enumerate(zip(probs, wls)):
+        zo, Lo, _ = oracle_ref(wl["H"], wl["y"], pb.K, pb.Q, "mmse", pb.N0)
+        assert z_rel_err(host(z[j]), zo) <= Z_TOL_F32, j
+        assert llr_rel_err(host(L[j]), Lo) <= LLR_TOL_F32, j
+
+
 def test_jobs_persistent_schedule_matches(ocd):
     """The persistent schedule (workgroups popping tiles from the device queue)
     computes the same bits as one workgroup per tile."""
