@@ -10,10 +10,11 @@
 namespace ocd {
 
 // dLoss/dLLR of the mean binary cross-entropy softplus(L) - bit L over n bits
-// (P(bit = 1) = sigmoid(L)): (sigmoid(L) - bit) / n.
+// (P(bit = 1) = sigmoid(L)): (sigmoid(L) - bit) / n, for bit 1 as -sigmoid(-L) / n,
+// so that a confidently right bit keeps its small gradient instead of 1 - 1 = 0.
 __device__ __forceinline__ float bce_grad(float L, unsigned char bit, float inv_n)
 {
-    return (1.0f / (1.0f + expf(-L)) - (float)bit) * inv_n;
+    return (bit ? -1.0f / (1.0f + expf(L)) : 1.0f / (1.0f + expf(-L))) * inv_n;
 }
 
 // dLoss/dz of one user from dLoss/dLLR through L_b = rho * D_b(x), x = z/(mu sqrt(Es)),

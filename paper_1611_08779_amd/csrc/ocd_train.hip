@@ -16,10 +16,14 @@
 
 namespace ocd {
 
-// softplus(L) - bit L, the cross-entropy of one bit with P(bit = 1) = sigmoid(L)
+// softplus(L) - bit L, the cross-entropy of one bit with P(bit = 1) = sigmoid(L),
+// written as max(t, 0) + log(1 + e^-|L|) with t = L for bit 0 and -L for bit 1: a
+// bit that is confidently right costs the small second term alone, which the
+// subtraction softplus(L) - L would round away in FP32
 __device__ __forceinline__ float bce_term(float L, unsigned char bit)
 {
-    return fmaxf(L, 0.f) + log1pf(expf(-fabsf(L))) - (bit ? L : 0.f);
+    const float t = bit ? -L : L;
+    return fmaxf(t, 0.f) + log1pf(expf(-fabsf(L)));
 }
 
 template <int L, int NPL, bool F16, bool BOX, int UC>

@@ -49,5 +49,6 @@ def one_sided(evaluate, theta0, h0=None):
 
 
 def bce_sum(L, bits):
-    """Sum over bits of softplus(L) - bit * L (P(bit = 1) = sigmoid(L))."""
-    return float(np.sum(np.logaddexp(0.0, L) - bits * L))
+    """Sum over bits of softplus(L) - bit * L (P(bit = 1) = sigmoid(L)), formed as
+    softplus(-L) for bit 1, which does not cancel when the bit is confidently right."""
+    return float(np.sum(np.logaddexp(0.0, np.where(bits != 0, -L, L))))

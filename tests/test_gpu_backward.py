@@ -36,7 +36,7 @@ def rel(a, b):
 
 
 def _bce(L, bits):
-    return float(np.mean(np.logaddexp(0.0, L) - bits * L))
+    return float(np.mean(np.logaddexp(0.0, np.where(bits != 0, -L, L))))
 
 
 def _case(ocd, mode, B=128, U=16, W=32, S=4, Q=4, K=4, snr=10.0, seed=0):

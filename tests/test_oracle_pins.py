@@ -364,8 +364,9 @@ def test_constellation_gray_neighbours_differ_in_one_bit():
 # ---------------------------------------------------------------- gradients
 
 def _bce_loss(L, bits):
-    # mean over bits of softplus(L) - bit * L  (P(bit = 1) = sigmoid(L))
-    return float(np.mean(np.logaddexp(0.0, L) - bits * L))
+    # mean over bits of softplus(L) - bit * L  (P(bit = 1) = sigmoid(L)); softplus(-L)
+    # for bit 1, which does not cancel when the bit is confidently right
+    return float(np.mean(np.logaddexp(0.0, np.where(bits != 0, -L, L))))
 
 
 def _forward_loss(H, y, bits, K, Q, mode, N0, lam, beta):
