@@ -87,6 +87,31 @@ def test_noalloc_adjoint_matches_the_workspace_form_twice(ocd, order):
             assert r[0][0] != 0.0 or r[1][0] != 0.0
 
 
+def test_noalloc_adjoint_over_a_random_sequence_of_shapes(ocd):
+    """Twelve calls in a row on the shared scratch, seeded random shapes growing and
+    shrinking (B, U, W, S, Q, K and the mode drawn; each within the scratch): every
+    call equals the workspace form bit for bit, whatever the previous call left."""
+    rng = np.random.default_rng(20261209)
+    for n in range(12):
+        B = int(rng.integers(2, 257))
+        U = int(rng.integers(1, max(1, min(32, B // 2)) + 1))
+        S = int(rng.integers(1, 9))
+        W = int(rng.integers(1, max(1, 400 // S) + 1))
+        Q, K = int(rng.choice([2, 4, 6])), int(rng.integers(1, 6))
+        mode = str(rng.choice(["mmse", "box", "hybrid"]))
+        say("noalloc sequence %d: B=%d U=%d W=%d S=%d Q=%d K=%d %s" % (n, B, U, W, S, Q, K, mode))
+        pb, H, y, lam, zh, bits = _problem(ocd, B, U, W, S, Q, K, mode, 100 + n)
+        ws = torch.zeros(ocd.ocd_backward_workspace_bytes(pb), dtype=torch.uint8, device="cuda")
+        ref, got = _outputs(pb), _outputs(pb)
+        ocd.ocd_detect_backward_bce(pb, H, y, lam, zh, bits, *ref, ws)
+        ocd.ocd_detect_backward_bce_noalloc(pb, H, y, lam, zh, bits, *got)
+        torch.cuda.synchronize()
+        for name, a, b in zip(("dlambda", "dbeta", "dy"), [host(t) for t in got],
+                              [host(t) for t in ref]):
+            assert np.all(np.isfinite(a)), (n, name)
+            assert np.array_equal(a, b), (n, name)
+
+
 def test_noalloc_adjoint_rejects_what_does_not_fit_and_handles_empty(ocd):
     # 2^22 subcarriers x 4 symbols: several hundred thousand workgroups of partial sums,
     # far beyond the scratch; rejected on the host before anything is read or launched
