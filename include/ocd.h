@@ -45,6 +45,10 @@
  * nothing was launched and no output was touched.  OCD_EDEVICE reports a HIP
  * runtime error from a launch (outputs are then unspecified).  Nothing throws,
  * aborts or prints across the ABI.
+ *
+ * Building against it.  The header is C99 as well as C++.  It includes
+ * <hip/hip_runtime_api.h> for hipStream_t, which a compiler other than hipcc
+ * reads with -D__HIP_PLATFORM_AMD__ -I/opt/rocm/include; link with -locd.
  */
 #ifndef OCD_H
 #define OCD_H

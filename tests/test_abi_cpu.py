@@ -38,6 +38,46 @@ def test_header_declares_the_boundary():
         assert required in names
 
 
+C_CALLER = r'''
+#include "ocd.h"
+#include <stdio.h>
+int main(void)
+{
+    ocd_problem pb = {128, 8, 1200, 14, 6, 3, OCD_MMSE, OCD_STORE_F32, 0.01f, 1.0f, 0.0f};
+    ocd_problem bad = pb;
+    ocd_plan pl;
+    bad.Q = 5;
+    if (ocd_get_plan(&pb, &pl) != OCD_OK || pl.lanes_per_vector < 4) return 1;
+    if (ocd_backward_workspace_bytes(&pb) != 256 + 16800u * 5u * 4u) return 2;
+    if (ocd_get_plan(&bad, &pl) != OCD_EINVAL) return 3;
+    printf("%s %d\n", ocd_status_str(OCD_OK), ocd_version());
+    return 0;
+}
+'''
+
+
+def test_header_compiles_as_c99_and_a_c_program_links(tmp_path, lib):
+    """The boundary is plain C: a C99 program includes ocd.h, links libocd.so and
+    calls the host-side entry points (no GPU needed for these)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "caller.c"
+    src.write_text(C_CALLER)
+    exe = tmp_path / "caller"
+    libdir = os.path.dirname(LIB)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Werror=implicit-function-declaration",
+                        "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROOT, "include"),
+                        "-I/opt/rocm/include", str(src), "-o", str(exe), "-L" + libdir, "-locd",
+                        "-Wl,-rpath," + libdir], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert run.returncode == 0, (run.returncode, run.stdout, run.stderr)
+    assert run.stdout.startswith("OCD_OK")
+
+
 def test_every_declared_symbol_is_exported(lib):
     for name in _declared_functions():
         assert hasattr(lib, name), name
