@@ -6,19 +6,21 @@ sharing H_w, 64-QAM, K=3 sweeps, MMSE, 20 dB, FP32 storage (synthetic
 Rayleigh-fading slots).  A step is one fused launch of the whole path (stage
 H_w, preprocessing, Algorithm 1, soft output, stores) over one slot of 16,800
 vectors; consecutive steps cycle through distinct slots (> 1 GB in total) so the
-256 MB Infinity Cache cannot hold the inputs.  The timed steps are captured in
-a hipGraph (through torch.cuda.CUDAGraph) and replayed, so host launch overhead
-is not timed; the kernel's own duration is measured with per-launch HIP events
-on its stream.
+256 MB Infinity Cache cannot hold the inputs.  The launch plan is tuned over
+those slots (ocd_autotune_inputs), the regime the steps run in.  The timed steps
+are captured in a hipGraph (through torch.cuda.CUDAGraph) and replayed, so host
+launch overhead is not timed; HIP events on the replay stream bracket exactly
+the timed steps, and the kernel's average launch time is that region divided by
+its launches (one per step).
 
 One JSON line goes to stdout; progress goes to stderr.  Besides the contract's
 fields it carries the roofline of the dominant kernel, the FP64 oracle timed on
 this host's cores, and the other forms: FP16 storage (speedup at equal BER),
 the S=1 variant (one H per vector, HBM-bound), the OFDM front end (alone and
-followed by detection), the paper's 16-bit fixed-point datapath, explicit MMSE detection (the detector OCD approximates, at paired bit
-errors), 48 uneven jobs in one persistent
-graph launch against one launch per job, and the forward+backward step of the
-differentiable form in vectors/s.
+followed by detection), the paper's 16-bit fixed-point datapath, explicit MMSE
+detection (the detector OCD approximates, at paired bit errors), 48 uneven jobs
+in one graph launch against one launch per job, the forward+backward step of the
+differentiable form in vectors/s, and the measured FP32 FMA and device-copy rates.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--main-only]
 """
