@@ -12,9 +12,11 @@
 //   out[(j / Ns) Ns R + k + q Ns] = sum_r v_r exp(-2 pi i r q / R).
 // The first pass reads its operands straight from HBM (in[t + r N/8] is the
 // time-domain symbol after the prefix); the passes exchange through LDS.  Each
-// pass loads one twiddle w = exp(-2 pi i k / (Ns R)) per butterfly from a
-// 4096-entry table (built at compile time in double precision, rounded to FP32)
-// and forms w^2 .. w^(R-1) by complex products.
+// butterfly takes one twiddle w = exp(-2 pi i k / (Ns R)) from a 4096-entry table
+// (built at compile time in double precision, rounded to FP32) and forms
+// w^2 .. w^(R-1) by complex products.  A thread's twiddles for all of its passes
+// are loaded at the start, with its operands: loaded after each pass's barrier,
+// every pass waited for an L2 round trip in the workgroup's serial chain.
 //
 // Consecutive subcarriers are S B entries apart in y, so one FFT's outputs are
 // scattered.  A workgroup holds the FFTs of consecutive antennas of one symbol
@@ -201,6 +203,18 @@ __global__ __launch_bounds__(NT) void k_ofdm_fft(OfdmParams P)
     float2 v[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = x[t + r * T];
+    // the twiddles of every later pass depend only on t: their table loads go out
+    // with the operands', so no pass waits on memory after its barrier
+    float2 tw8[Sh::P8 > 1 ? Sh::P8 - 1 : 1];
+#pragma unroll
+    for (int pass = 1, ns = 8; pass < Sh::P8; ++pass, ns *= 8)
+        tw8[pass - 1] = twiddle<N>((t & (ns - 1)) * (N / (ns * 8)));
+    constexpr int NREM = Sh::REM == 2 ? 2 : Sh::REM == 1 ? 4 : 1;
+    float2 twr[NREM];
+    if constexpr (Sh::REM != 0) {
+#pragma unroll
+        for (int h = 0; h < NREM; ++h) twr[h] = twiddle<N>(t + h * T);
+    }
     dft8(v);
 #pragma unroll
     for (int q = 0; q < 8; ++q) sh[lds_index(8 * t + q)] = v[q];
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_ofdm_fft(OfdmParams P)
 #pragma unroll
         for (int r = 0; r < 8; ++r) v[r] = sh[lds_index(j + r * T)];
         __syncthreads();
-        twiddle_powers<8>(v, twiddle<N>(k * (N / (Ns * 8))));
+        twiddle_powers<8>(v, tw8[pass - 1]);
         dft8(v);
         const int base = (j / Ns) * Ns * 8 + k;
 #pragma unroll
@@ -236,7 +250,7 @@ __global__ __launch_bounds__(NT) void k_ofdm_fft(OfdmParams P)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int j = t + h * T;
-            twiddle_powers<4>(u[h], twiddle<N>(j));
+            twiddle_powers<4>(u[h], twr[h]);
             dft4(u[h][0], u[h][1], u[h][2], u[h][3]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) sh[lds_index(j + q * (N / 4))] = u[h][q];
@@ -255,7 +269,7 @@ __global__ __launch_bounds__(NT) void k_ofdm_fft(OfdmParams P)
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             const int j = t + h * T;
-            twiddle_powers<2>(u[h], twiddle<N>(j));
+            twiddle_powers<2>(u[h], twr[h]);
             sh[lds_index(j)] = cadd(u[h][0], u[h][1]);
             sh[lds_index(j + N / 2)] = csub(u[h][0], u[h][1]);
         }
