@@ -432,7 +432,7 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="L,VPB[,XCD[,STAGGER]]: fix the launch plan instead of autotuning "
                          "(profiled runs, so that every traced launch of the kernel is the timed one)")
-    ap.add_argument("--mmse-only", default=None, metavar="L,VPB",
+    ap.add_argument("--mmse-only", default=None, metavar="L,VPB[,XCD[,STAGGER]]",
                     help="only the explicit-MMSE detector on the headline slots with this plan "
                          "(profiled runs); prints its own JSON line")
     ap.add_argument("--ofdm-only", action="store_true",
@@ -519,8 +519,8 @@ def main():
         print(json.dumps(res), flush=True)
         return
     if args.mmse_only:
-        f = [int(x) for x in args.mmse_only.split(",")] + [0]
-        mp = ocd.Plan(f[0], f[1], f[2], 0)
+        f = [int(x) for x in args.mmse_only.split(",")] + [0, 0]
+        mp = ocd.Plan(f[0], f[1], f[2], 0, f[3])
         pbm = ocd.problem(B, U, W, S, Q, 1, "mmse", "f32", N0)
         fns = [(lambda i=i: ocd.ocd_detect_mmse(pbm, slots[i]["H"], slots[i]["y"], outs[i][0],
                                                 outs[i][1], mp)) for i in range(len(slots))]
@@ -736,7 +736,7 @@ def mmse_form(torch, ocd, synth, dev, args, slots, pb32, t_ocd, errs_ocd, nbits)
         the input sets in turn (inputs read from HBM), not one cache-resident set."""
         best = None
         for c in cands:
-            pl = ocd.Plan(c[0], c[1], c[2], 0)
+            pl = ocd.Plan(c[0], c[1], c[2], 0, c[3] if len(c) > 3 else 0)
             fs = [(lambda i=i: ocd.ocd_detect_mmse(prob, ins[i]["H"], ins[i]["y"], o[i][0],
                                                    o[i][1], pl)) for i in range(len(ins))]
             try:

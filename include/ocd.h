@@ -369,7 +369,7 @@ ocd_status ocd_jobs_schedule(const ocd_problem *jobs, int n_jobs, int *persisten
  *               or lanes_per_vector 0 with vectors_per_block 0 or S: one subcarrier
  *               per workgroup, the Gram matrix and the S matched filters as real
  *               matrix products on the FP32 matrix cores (U <= 8, S <= 16).
- *               xcd_remap honoured; channel_in_registers must be 0.  NULL: lane
+ *               xcd_remap and stagger honoured; channel_in_registers must be 0.  NULL: lane
  *               groups with whole subcarriers per workgroup where they fit.  OCD_EUNSUPPORTED if the
  *               plan does not fit the problem or its LDS exceeds the device's
  *               per-workgroup limit.

@@ -616,14 +616,16 @@ def train_step(H, y, bits, K, Q, mode="hybrid", N0=1.0, Es=1.0, beta=0.0, lam=No
 def detect_mmse(H, y, Q, N0=1.0, Es=1.0, storage="f32", want_z=True, want_llr=True, plan=None,
                 stream=None):
     """Runs ocd_detect_mmse (explicit MMSE, exact soft output); returns (z, llr) with None
-    for outputs not asked for.  plan: a Plan, an (L, vectors_per_block[, xcd]) tuple or None."""
+    for outputs not asked for.  plan: a Plan, an (L, vectors_per_block[, xcd[, stagger]])
+    tuple or None."""
     W, U, B, S = _shape_of(H, y, storage)
     pb = problem(B, U, W, S, Q, 1, "mmse", storage, N0, Es)
     dev = H.device
     z = torch.empty(W, S, U, device=dev, dtype=torch.complex64) if want_z else None
     llr = torch.empty(W, S, U, Q, device=dev, dtype=torch.float32) if want_llr else None
     if plan is not None and not isinstance(plan, Plan):
-        plan = Plan(int(plan[0]), int(plan[1]), int(plan[2]) if len(plan) > 2 else 0, 0)
+        plan = Plan(int(plan[0]), int(plan[1]), int(plan[2]) if len(plan) > 2 else 0, 0,
+                    int(plan[3]) if len(plan) > 3 else 0)
     ocd_detect_mmse(pb, H, y, z, llr, plan, stream)
     return z, llr
 

@@ -430,6 +430,7 @@ static bool make_mmse_mfma_params(const ocd_problem *pb, const ocd_plan &pl, Par
     if (pl.lanes_per_vector != 0 || pl.channel_in_registers != 0) return false;
     if (pb->U > 8 || pb->S > 16) return false;
     if (pl.vectors_per_block != 0 && pl.vectors_per_block != pb->S) return false;
+    if (pl.stagger < 0 || pl.stagger > 16) return false;
     std::memset(&P, 0, sizeof(P));
     P.B = pb->B; P.U = pb->U; P.W = pb->W; P.S = pb->S; P.K = pb->K; P.Q = pb->Q;
     P.Bpad = (pb->B + 3) / 4 * 4;
@@ -437,6 +438,7 @@ static bool make_mmse_mfma_params(const ocd_problem *pb, const ocd_plan &pl, Par
     P.maxslots = 1;
     P.nblocks = pb->W;
     P.xcd_remap = pl.xcd_remap ? 1 : 0;
+    P.stagger = pl.stagger;
     P.Es = pb->Es; P.N0 = pb->N0;
     P.lam_default = pb->N0 / pb->Es;
     P.sqEs = std::sqrt(pb->Es);

@@ -125,6 +125,7 @@ __global__ __launch_bounds__(512) void k_mmse(Params P)
     extern __shared__ __align__(16) unsigned char smem[];
     const MmseSmem sm = mmse_carve(smem, P);
     const int bid = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    stagger_loads(P);
     const Tile tile = tile_of(P, bid);
     const int U = P.U, Bpad = P.Bpad, E = U * U;
     const int grp = threadIdx.x / L, j = threadIdx.x % L, ngrp = blockDim.x / L;
@@ -258,6 +259,7 @@ __global__ __launch_bounds__(256) void k_mmse_mfma(Params P)
     float2 *sv = lc + U;                                  // [S][U]
     float *gd = reinterpret_cast<float *>(sv + (size_t)S * U);
     const int w = P.xcd_remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    stagger_loads(P);
     const int tid = threadIdx.x;
 
     // stage X and Z antenna-major, zero-padded: thread tid takes antenna b = tid
@@ -355,20 +357,49 @@ __global__ __launch_bounds__(256) void k_mmse_mfma(Params P)
     }
 }
 
+// Staggered staging (plan field stagger) delays only the workgroups resident at
+// launch: the occupancy of this kernel at this shape gives their count.
+static hipError_t with_stagger_cap(const void *fn, int threads, size_t lds, Params &q)
+{
+    if (q.stagger <= 0) return hipSuccess;
+    int per_cu = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+    if (e != hipSuccess) return e;
+    q.stagger_cap = per_cu * device_cu_count();
+    return hipSuccess;
+}
+
+template <bool F16>
+static hipError_t launch_mmse_mfma_t(const Params &p, size_t lds, hipStream_t s)
+{
+    Params q = p;
+    const hipError_t e = with_stagger_cap(reinterpret_cast<const void *>(k_mmse_mfma<F16>), 256, lds, q);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_mmse_mfma<F16>), dim3(q.nblocks), dim3(256), lds, s, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_mmse_mfma(bool f16, const Params &p, size_t lds, hipStream_t s)
 {
-    if (f16) hipLaunchKernelGGL((k_mmse_mfma<true>), dim3(p.nblocks), dim3(256), lds, s, p);
-    else hipLaunchKernelGGL((k_mmse_mfma<false>), dim3(p.nblocks), dim3(256), lds, s, p);
+    return f16 ? launch_mmse_mfma_t<true>(p, lds, s) : launch_mmse_mfma_t<false>(p, lds, s);
+}
+
+template <int L, int NPL, bool F16>
+static hipError_t launch_mmse_f(const Params &p, int threads, size_t lds, hipStream_t s)
+{
+    Params q = p;
+    const hipError_t e =
+        with_stagger_cap(reinterpret_cast<const void *>(k_mmse<L, NPL, F16>), threads, lds, q);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_mmse<L, NPL, F16>), dim3(q.nblocks), dim3(threads), lds, s, q);
     return hipGetLastError();
 }
 
 template <int L, int NPL>
 static hipError_t launch_mmse_t(bool f16, const Params &p, int threads, size_t lds, hipStream_t s)
 {
-    const dim3 grid(p.nblocks), block(threads);
-    if (f16) hipLaunchKernelGGL((k_mmse<L, NPL, true>), grid, block, lds, s, p);
-    else hipLaunchKernelGGL((k_mmse<L, NPL, false>), grid, block, lds, s, p);
-    return hipGetLastError();
+    return f16 ? launch_mmse_f<L, NPL, true>(p, threads, lds, s)
+               : launch_mmse_f<L, NPL, false>(p, threads, lds, s);
 }
 
 template <int L>

@@ -287,6 +287,12 @@ def test_mmse_detector_checks_its_arguments_on_the_host(lib):
     assert call(dict(U=9), plan=(0, 14, 0, 0)) == -2
     assert call(dict(S=17), plan=(0, 17, 0, 0)) == -2
     assert call(dict(W=0), plan=(16, 14, 0, 0)) == 0    # nothing to do
+    # staggered staging, both forms: 0..16 accepted, anything else refused
+    assert call(dict(W=0), plan=(16, 14, 0, 0, 4)) == 0
+    assert call(dict(W=0), plan=(0, 14, 0, 0, 16)) == 0
+    assert call(plan=(16, 14, 0, 0, 17)) == -2
+    assert call(plan=(0, 14, 0, 0, 17)) == -2
+    assert call(plan=(0, 14, 0, 0, -1)) == -2
 
 
 @pytest.mark.parametrize("B,U,S", [(512, 8, 2), (256, 16, 3), (128, 8, 14), (64, 32, 2), (33, 4, 2),

@@ -64,7 +64,8 @@ def run_mmse(ocd, B, U, W, S, Q, snr, seed, Es=1.0, plan=None, ztol=None, ltol=N
 
 # the headline shape on a slice of subcarriers, under several plans
 @pytest.mark.parametrize("plan", [None, (0, 14, 0), (0, 0, 1), (16, 14, 0), (16, 28, 1), (16, 16, 0),
-                                  (8, 14, 0), (32, 14, 0), (16, 5, 0)])
+                                  (8, 14, 0), (32, 14, 0), (16, 5, 0),
+                                  (8, 14, 0, 2), (16, 14, 1, 4), (0, 14, 0, 4)])   # staggered
 def test_b128_u8_s14_64qam_plans(ocd, plan):
     run_mmse(ocd, 128, 8, 60, 14, 6, 20.0, [50, 1], plan=plan)
 
@@ -136,13 +137,15 @@ def test_outputs_are_optional_and_consistent(ocd):
     assert torch.equal(z, z1) and torch.equal(L, L1)
 
 
-def test_headline_full_size_sampled(ocd):
+@pytest.mark.parametrize("plan", [None, (8, 14, 0, 2), (0, 14, 0, 4)])
+def test_headline_full_size_sampled(ocd, plan):
     """B=128, U=8, 1200 subcarriers x 14 symbols, 64-QAM, 20 dB: the whole slot on
-    the GPU with the launch bench.py times; a sample of subcarriers on the oracle."""
+    the GPU (default plan, and staggered plans of both forms: every workgroup past
+    the first 256 waits before its loads); a sample of subcarriers on the oracle."""
     B, U, W, S, Q = 128, 8, 1200, 14, 6
     wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[57])
     N0 = f32(wl["N0"])
-    z, L = ocd.detect_mmse(dev(wl["H"]), dev(wl["y"]), Q, N0)
+    z, L = ocd.detect_mmse(dev(wl["H"]), dev(wl["y"]), Q, N0, plan=plan)
     torch.cuda.synchronize()
     ws = np.random.default_rng(57).choice(W, 24, replace=False)
     zo, Lo, _ = oracle.mmse(wl["H"][ws], wl["y"][ws], Q, N0=N0, threads=0)
