@@ -258,8 +258,11 @@ ocd_status ocd_train_plan(const ocd_problem *pb, ocd_plan *plan);
 ocd_status ocd_set_plan(const ocd_problem *pb, const ocd_plan *plan);
 
 /* Autotuner: times every valid plan for this problem on the caller's buffers
- * (outputs are overwritten; z and llr must be non-NULL), caches the fastest
- * for the shape (with and without per-sweep regularisers) and returns it.  Synchronises `stream`.  When the environment
+ * (outputs are overwritten; z and llr must be non-NULL), after ~20 ms of launches
+ * that bring the clocks to their loaded level; then re-times the four fastest,
+ * each with stagger 0, 1, 2 and 4, in three interleaved rounds, caches the one
+ * with the lowest median for the shape (with and without per-sweep regularisers)
+ * and returns it.  Synchronises `stream`.  When the environment
  * variable OCD_TUNE_CACHE names a file, plans are also loaded from and saved
  * to that JSON file, keyed by GPU architecture and shape. */
 ocd_status ocd_autotune(const ocd_problem *pb, const void *H, const void *y,
