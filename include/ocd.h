@@ -318,8 +318,9 @@ ocd_status ocd_autotune_backward(const ocd_problem *pb, const void *H, const voi
  *               so a change of pointers only re-uploads the tables).
  *               OCD_JOBS_TUNE: before running, time every schedule, tile-size
  *               policy and lane mode on the caller's buffers (outputs are
- *               overwritten; synchronises `stream`) and keep the fastest for this
- *               list of shapes.
+ *               overwritten; synchronises `stream`), time the fastest three again
+ *               in three interleaved rounds, and keep the one with the lowest
+ *               median for this list of shapes.
  *               OCD_JOBS_PERSISTENT: use the persistent schedule.
  *               OCD_JOBS_LANE_MODE(m), m = 0, 1, 2: use lane mode m (below)
  *               instead of the tuned one.

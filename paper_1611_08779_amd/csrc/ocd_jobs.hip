@@ -502,19 +502,42 @@ extern "C" ocd_status ocd_detect_jobs(const ocd_problem *jobs, const void *const
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return OCD_EDEVICE;
         if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return OCD_EDEVICE; }
-        float best_ms = 1e30f;
-        int best = choice;
-        for (int c = 0; c < N_CHOICES; ++c) {
-            ocd_status st = run_choice(jobs, n_jobs, c, H, y, z, llr, ws, workspace_bytes, false, stream);
-            if (st != OCD_OK) continue;
+        // three launches of a choice, timed (ms; < 0 if the choice does not run)
+        auto time_choice = [&](int c) -> float {
+            ocd_status st = OCD_OK;
             (void)hipEventRecord(e0, stream);
             for (int rep = 0; rep < 3 && st == OCD_OK; ++rep)
                 st = run_choice(jobs, n_jobs, c, H, y, z, llr, ws, workspace_bytes, false, stream);
             (void)hipEventRecord(e1, stream);
-            if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) continue;
+            if (st != OCD_OK || hipEventSynchronize(e1) != hipSuccess) return -1.f;
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) { best_ms = ms; best = c; }
+            return ms;
+        };
+        std::vector<std::pair<float, int>> ranked;
+        for (int c = 0; c < N_CHOICES; ++c) {
+            if (run_choice(jobs, n_jobs, c, H, y, z, llr, ws, workspace_bytes, false, stream) != OCD_OK)
+                continue;
+            const float ms = time_choice(c);
+            if (ms >= 0.f) ranked.push_back({ms, c});
+        }
+        // the fastest three again, in three interleaved rounds: the lowest median
+        // wins (the schedules are often within a few percent of each other)
+        int best = choice;
+        if (!ranked.empty()) {
+            std::sort(ranked.begin(), ranked.end());
+            const int nf = (int)std::min<size_t>(3, ranked.size());
+            float t[3][3] = {};
+            for (int rd = 0; rd < 3; ++rd)
+                for (int k = 0; k < nf; ++k) {
+                    const int f = rd % 2 ? nf - 1 - k : k;
+                    t[f][rd] = time_choice(ranked[f].second);
+                }
+            float best_med = 1e30f;
+            for (int f = 0; f < nf; ++f) {
+                std::sort(t[f], t[f] + 3);
+                if (t[f][0] >= 0.f && t[f][1] < best_med) { best_med = t[f][1]; best = ranked[f].second; }
+            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
