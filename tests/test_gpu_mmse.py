@@ -209,3 +209,18 @@ def test_matrix_core_form_rejects_shapes_it_does_not_cover(ocd):
     wl = synth.make_workload(64, 8, 4, 4, 4, 10.0, seed=[61])
     with pytest.raises(ocd.OCDError):
         ocd.detect_mmse(dev(wl["H"]), dev(wl["y"]), 4, 0.1, plan=(0, 2))     # not S
+
+
+@pytest.mark.parametrize("base", [(8, 14, 0), (16, 28, 1), (0, 14, 0)])
+def test_stagger_changes_only_when_workgroups_start(ocd, base):
+    """Staggered staging delays workgroups before their loads and nothing else: the
+    outputs of both forms are bit-identical at every stagger value."""
+    B, U, W, S, Q = 128, 8, 600, 14, 6
+    wl = synth.make_workload(B, U, W, S, Q, 20.0, seed=[59])
+    N0 = f32(wl["N0"])
+    H, y = dev(wl["H"]), dev(wl["y"])
+    z0, L0 = ocd.detect_mmse(H, y, Q, N0, plan=base + (0,))
+    for sg in (1, 2, 4, 16):
+        z, L = ocd.detect_mmse(H, y, Q, N0, plan=base + (sg,))
+        torch.cuda.synchronize()
+        assert torch.equal(z, z0) and torch.equal(L, L0), sg
