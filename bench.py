@@ -714,7 +714,7 @@ def fixed_form(torch, ocd, dev, args, slots, pb32, t_ocd, errs_ocd, nbits):
                for i in range(len(slots)))
     return {"gbps": W * S * U * Q / t / 1e9, "ms_per_step": t * 1e3, "eager_launch_us": tk * 1e6,
             "slowdown_vs_fp32": t / t_ocd, "bit_errors_fixed": errs, "bit_errors_fp32": errs_ocd,
-            "bits": nbits, "kernel": "ocd::k_forward_fx<32, 4>",
+            "bits": nbits, "kernel": "ocd::k_forward_fx<16, 8, true>",
             "inputs": "Q5.11 int16 pairs of sqrt(B) H and sqrt(B) y, N0 B"}
 
 

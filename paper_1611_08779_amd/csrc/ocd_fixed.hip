@@ -19,10 +19,12 @@
 // is exact, a floor after a power-of-two scale is the arithmetic shift, and
 // clamps are the saturation; MI355X runs FP64 FMAs at the FP32 vector rate.  The
 // sums are exact, so the order of the cross-lane sums does not matter and the
-// result is bit-exact.  H is read from global memory at every update: the S
-// symbols of a subcarrier read the same columns, which stay in the caches.
+// result is bit-exact.  The H_w a workgroup touches are staged in LDS as the int16
+// pairs they are (where they fit in 32 KB), so that an update's column read is an
+// LDS read rather than a round trip to the L2.
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "ocd_api_internal.h"
@@ -119,17 +121,34 @@ __device__ __forceinline__ long long group_sum_i64(long long x)
     return x;
 }
 
-template <int L, int NPL>
+// STAGED: the H_w of the subcarriers a workgroup touches are copied into LDS once
+// (the int16 pairs as they are), and every update reads its column there;
+// otherwise (channels too large for the LDS budget) each update reads its column
+// from global memory, where the S symbols of a subcarrier share it through the
+// caches.  The arithmetic is the same either way.
+template <int L, int NPL, bool STAGED>
 __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
 {
     constexpr int G = 256 / L;
     __shared__ int zs[G][32][2];
     __shared__ int ds[G][32], ps[G][32];
     __shared__ long long gs[G][32];
+    extern __shared__ __align__(16) uint32_t hst[];  // STAGED: [slots][U][B] int16 pairs
     const int grp = threadIdx.x / L, j = threadIdx.x % L;
     const long v = (long)blockIdx.x * G + grp;
-    if (v >= (long)P.W * P.S) return;   // a whole lane group at once
+    const long nvec = (long)P.W * P.S;
     const int U = P.U, B = P.B, b = P.b;
+    const uint32_t *Hs = nullptr;
+    if constexpr (STAGED) {
+        const long v0 = (long)blockIdx.x * G, vl = (v0 + G < nvec ? v0 + G : nvec) - 1;
+        const long w_first = v0 / P.S;
+        const int total = (int)(vl / P.S - w_first + 1) * U * B;
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(P.H) + (size_t)w_first * U * B;
+        for (int i = threadIdx.x; i < total; i += blockDim.x) hst[i] = src[i];
+        __syncthreads();
+        Hs = hst + (size_t)((v < nvec ? v : v0) / P.S - w_first) * U * B;
+    }
+    if (v >= nvec) return;   // a whole lane group at once
     const int16_t *Hw = P.H + (size_t)(v / P.S) * U * B * 2;
     const int16_t *yv = P.y + (size_t)v * B * 2;
 
@@ -167,7 +186,7 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
 
     // column entries as (re, im) int16 pairs in one dword; lanes past B hold 0
     auto load_col = [&](int u, uint32_t (&h)[NPL]) {
-        const uint32_t *hu = reinterpret_cast<const uint32_t *>(Hw) + (size_t)u * B;
+        const uint32_t *hu = (STAGED ? Hs : reinterpret_cast<const uint32_t *>(Hw)) + (size_t)u * B;
 #pragma unroll
         for (int i = 0; i < NPL; ++i) {
             const int a = j + L * i;
@@ -256,25 +275,34 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
     }
 }
 
+// Channels are staged when the subcarriers a workgroup can touch fit in 32 KB of
+// LDS (B = 128, U = 8, S = 14: two subcarriers, 8 KB).
 template <int L, int NPL>
 static hipError_t launch_fx_t(const FxParams &p, hipStream_t s)
 {
     constexpr int G = 256 / L;
     const long nvec = (long)p.W * p.S;
-    hipLaunchKernelGGL((k_forward_fx<L, NPL>), dim3((unsigned)((nvec + G - 1) / G)), dim3(256), 0,
-                       s, p);
+    const dim3 grid((unsigned)((nvec + G - 1) / G));
+    const long slots = std::min<long>(G, (G - 1) / p.S + 2);
+    const size_t lds = (size_t)slots * p.U * p.B * sizeof(uint32_t);
+    if (lds <= 32768)
+        hipLaunchKernelGGL((k_forward_fx<L, NPL, true>), grid, dim3(256), lds, s, p);
+    else
+        hipLaunchKernelGGL((k_forward_fx<L, NPL, false>), grid, dim3(256), 0, s, p);
     return hipGetLastError();
 }
 
-// 16 lanes per vector up to B = 64, 32 above: each update is a serial chain (64-bit
-// sums across the group, then the narrowing), so beyond 4 entries per lane more,
-// shorter lanes hide it better (B = 128: 88 -> 84 us, B = 256: 199 -> 154 us per
-// 16,800 vectors; B = 64 is faster at 16 lanes, 51 against 63 us).
+// 16 lanes per vector up to B = 128, 32 above: each update is a serial chain (64-bit
+// sums across the group, then the narrowing), so with many entries per lane more,
+// shorter lanes hide it better (B = 256: 199 -> 154 us per 16,800 vectors at 32
+// lanes; B = 64 is faster at 16 lanes, 51 against 63 us).  At B = 128 the columns'
+// global-memory round trips made 32 lanes the faster (88 against 84 us); with the
+// columns staged in LDS, 16 lanes are: 77.5 against 80.1 us.
 static hipError_t launch_fx(const FxParams &p, hipStream_t s)
 {
     if (p.B <= 32) return launch_fx_t<16, 2>(p, s);
     if (p.B <= 64) return launch_fx_t<16, 4>(p, s);
-    if (p.B <= 128) return launch_fx_t<32, 4>(p, s);
+    if (p.B <= 128) return launch_fx_t<16, 8>(p, s);
     if (p.B <= 256) return launch_fx_t<32, 8>(p, s);
     if (p.B <= 512) return launch_fx_t<32, 16>(p, s);
     return launch_fx_t<32, 32>(p, s);
