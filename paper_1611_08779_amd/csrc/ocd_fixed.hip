@@ -19,9 +19,10 @@
 // is exact, a floor after a power-of-two scale is the arithmetic shift, and
 // clamps are the saturation; MI355X runs FP64 FMAs at the FP32 vector rate.  The
 // sums are exact, so the order of the cross-lane sums does not matter and the
-// result is bit-exact.  The H_w a workgroup touches are staged in LDS as the int16
-// pairs they are (where they fit in 32 KB), so that an update's column read is an
-// LDS read rather than a round trip to the L2.
+// result is bit-exact.  The H_w a workgroup touches are staged in LDS once, their
+// int16 values held exactly in FP32 (where they fit in 32 KB), so that an update's
+// column read is an LDS read rather than a round trip to the L2, and each entry
+// reaches FP64 in one conversion.
 #include <stdint.h>
 
 #include <algorithm>
@@ -122,7 +123,7 @@ __device__ __forceinline__ long long group_sum_i64(long long x)
 }
 
 // STAGED: the H_w of the subcarriers a workgroup touches are copied into LDS once
-// (the int16 pairs as they are), and every update reads its column there;
+// (int16 values held exactly in FP32), and every update reads its column there;
 // otherwise (channels too large for the LDS budget) each update reads its column
 // from global memory, where the S symbols of a subcarrier share it through the
 // caches.  The arithmetic is the same either way.
@@ -133,18 +134,21 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
     __shared__ int zs[G][32][2];
     __shared__ int ds[G][32], ps[G][32];
     __shared__ long long gs[G][32];
-    extern __shared__ __align__(16) uint32_t hst[];  // STAGED: [slots][U][B] int16 pairs
+    extern __shared__ __align__(16) float2 hst[];    // STAGED: [slots][U][B] int16 values in FP32
     const int grp = threadIdx.x / L, j = threadIdx.x % L;
     const long v = (long)blockIdx.x * G + grp;
     const long nvec = (long)P.W * P.S;
     const int U = P.U, B = P.B, b = P.b;
-    const uint32_t *Hs = nullptr;
+    const float2 *Hs = nullptr;
     if constexpr (STAGED) {
         const long v0 = (long)blockIdx.x * G, vl = (v0 + G < nvec ? v0 + G : nvec) - 1;
         const long w_first = v0 / P.S;
         const int total = (int)(vl / P.S - w_first + 1) * U * B;
         const uint32_t *src = reinterpret_cast<const uint32_t *>(P.H) + (size_t)w_first * U * B;
-        for (int i = threadIdx.x; i < total; i += blockDim.x) hst[i] = src[i];
+        for (int i = threadIdx.x; i < total; i += blockDim.x) {
+            const uint32_t e = src[i];
+            hst[i] = make_float2((float)(int16_t)(e & 0xFFFFu), (float)(int16_t)(e >> 16));
+        }
         __syncthreads();
         Hs = hst + (size_t)((v < nvec ? v : v0) / P.S - w_first) * U * B;
     }
@@ -186,26 +190,38 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
 
     // column entries as (re, im) int16 pairs in one dword; lanes past B hold 0
     auto load_col = [&](int u, uint32_t (&h)[NPL]) {
-        const uint32_t *hu = (STAGED ? Hs : reinterpret_cast<const uint32_t *>(Hw)) + (size_t)u * B;
+        const uint32_t *hu = reinterpret_cast<const uint32_t *>(Hw) + (size_t)u * B;
 #pragma unroll
         for (int i = 0; i < NPL; ++i) {
             const int a = j + L * i;
             h[i] = a < B ? hu[a] : 0u;
         }
     };
+    // the same column from the staged copy (int16 values held exactly in FP32)
+    auto load_col_s = [&](int u, float2 (&h)[NPL]) {
+        const float2 *hu = Hs + (size_t)u * B;
+#pragma unroll
+        for (int i = 0; i < NPL; ++i) {
+            const int a = j + L * i;
+            h[i] = a < B ? hu[a] : make_float2(0.f, 0.f);
+        }
+    };
     const double inv_b = ldexp(1.0, -b);
     uint32_t hn[NPL];
-    load_col(0, hn);
+    float2 hf[NPL];
+    if constexpr (STAGED) load_col_s(0, hf);
+    else load_col(0, hn);
     for (int k = 0; k < P.K; ++k)
         for (int u = 0; u < U; ++u) {
             double hr[NPL], hi[NPL];
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
-                hr[i] = (double)(int16_t)(hn[i] & 0xFFFFu);
-                hi[i] = (double)(int16_t)(hn[i] >> 16);
+                hr[i] = STAGED ? (double)hf[i].x : (double)(int16_t)(hn[i] & 0xFFFFu);
+                hi[i] = STAGED ? (double)hf[i].y : (double)(int16_t)(hn[i] >> 16);
             }
             // the next update's column is in flight while this one computes
-            load_col(u + 1 < U ? u + 1 : 0, hn);
+            if constexpr (STAGED) load_col_s(u + 1 < U ? u + 1 : 0, hf);
+            else load_col(u + 1 < U ? u + 1 : 0, hn);
             double ire = 0.0, iim = 0.0;   // h_u^H r, Q.22 integers
 #pragma unroll
             for (int i = 0; i < NPL; ++i) {
@@ -276,7 +292,7 @@ __global__ __launch_bounds__(256) void k_forward_fx(FxParams P)
 }
 
 // Channels are staged when the subcarriers a workgroup can touch fit in 32 KB of
-// LDS (B = 128, U = 8, S = 14: two subcarriers, 8 KB).
+// LDS (B = 128, U = 8, S = 14: two subcarriers, 16 KB).
 template <int L, int NPL>
 static hipError_t launch_fx_t(const FxParams &p, hipStream_t s)
 {
@@ -284,7 +300,7 @@ static hipError_t launch_fx_t(const FxParams &p, hipStream_t s)
     const long nvec = (long)p.W * p.S;
     const dim3 grid((unsigned)((nvec + G - 1) / G));
     const long slots = std::min<long>(G, (G - 1) / p.S + 2);
-    const size_t lds = (size_t)slots * p.U * p.B * sizeof(uint32_t);
+    const size_t lds = (size_t)slots * p.U * p.B * sizeof(float2);
     if (lds <= 32768)
         hipLaunchKernelGGL((k_forward_fx<L, NPL, true>), grid, dim3(256), lds, s, p);
     else
@@ -297,7 +313,7 @@ static hipError_t launch_fx_t(const FxParams &p, hipStream_t s)
 // shorter lanes hide it better (B = 256: 199 -> 154 us per 16,800 vectors at 32
 // lanes; B = 64 is faster at 16 lanes, 51 against 63 us).  At B = 128 the columns'
 // global-memory round trips made 32 lanes the faster (88 against 84 us); with the
-// columns staged in LDS, 16 lanes are: 77.5 against 80.1 us.
+// columns staged in LDS, 16 lanes are (77.5 against 80.1 us, int16 pairs staged).
 static hipError_t launch_fx(const FxParams &p, hipStream_t s)
 {
     if (p.B <= 32) return launch_fx_t<16, 2>(p, s);
