@@ -360,3 +360,62 @@ def test_fma_probe_checks_its_arguments_on_the_host(lib):
     assert lib.ocd_probe_fma(10, 0, d, ctypes.byref(fl), None) == -1
     assert lib.ocd_probe_fma(10, 10, None, ctypes.byref(fl), None) == -1
     assert lib.ocd_probe_fma(10, 10, d, None, None) == -1
+
+
+_CACHE_READER = r"""
+import ctypes, json, sys
+lib = ctypes.CDLL(sys.argv[1])
+class Problem(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int), ("U", ctypes.c_int), ("W", ctypes.c_int), ("S", ctypes.c_int),
+                ("Q", ctypes.c_int), ("K", ctypes.c_int), ("mode", ctypes.c_int),
+                ("storage", ctypes.c_int), ("N0", ctypes.c_float), ("Es", ctypes.c_float),
+                ("beta", ctypes.c_float)]
+class Plan(ctypes.Structure):
+    _fields_ = [("lanes_per_vector", ctypes.c_int), ("vectors_per_block", ctypes.c_int),
+                ("xcd_remap", ctypes.c_int), ("channel_in_registers", ctypes.c_int),
+                ("stagger", ctypes.c_int)]
+out = []
+for B, U, W, S, Q, K in json.loads(sys.argv[2]):
+    pb = Problem(B, U, W, S, Q, K, 0, 0, 0.01, 1.0, 0.0)
+    pl = Plan()
+    st = lib.ocd_get_plan(ctypes.byref(pb), ctypes.byref(pl))
+    out.append([st, pl.lanes_per_vector, pl.vectors_per_block, pl.xcd_remap,
+                pl.channel_in_registers, pl.stagger])
+print(json.dumps(out))
+"""
+
+
+def test_plan_cache_file_is_read(tmp_path):
+    """Plans persisted in the OCD_TUNE_CACHE file (one JSON object a line, keyed by
+    GPU architecture and shape) are what ocd_get_plan returns for those shapes: a
+    line written before the stagger field loads with stagger 0, a plan that is not
+    valid for its shape gives way to the heuristic, other lines are ignored.  Read
+    in a fresh process (the file is loaded once per process) with the GPUs hidden,
+    so that the architecture part of the key is "unknown"."""
+    import json
+    import subprocess
+    import sys
+    if not os.path.exists(LIB):
+        pytest.skip("libocd.so is not built")
+    key = "unknown|fwd|B%d|U%d|W%d|S%d|K%d|Q%d|m0|s0|l0"
+    shapes = [(128, 8, 1200, 14, 6, 3), (64, 4, 10, 2, 4, 2), (32, 4, 10, 2, 4, 2)]
+    lines = [
+        '{"key": "%s", "lanes_per_vector": 16, "vectors_per_block": 28, "xcd_remap": 1, '
+        '"channel_in_registers": 0, "stagger": 2}' % (key % (128, 8, 1200, 14, 3, 6)),
+        "not a plan",
+        '{"key": "%s", "lanes_per_vector": 8, "vectors_per_block": 4, "xcd_remap": 0, '
+        '"channel_in_registers": 0}' % (key % (64, 4, 10, 2, 2, 4)),
+        '{"key": "%s", "lanes_per_vector": 64, "vectors_per_block": 4, "xcd_remap": 0, '
+        '"channel_in_registers": 0, "stagger": 0}' % (key % (32, 4, 10, 2, 2, 4)),
+    ]
+    cache = tmp_path / "plans.json"
+    cache.write_text("\n".join(lines) + "\n")
+    env = dict(os.environ, OCD_TUNE_CACHE=str(cache), HIP_VISIBLE_DEVICES="-1",
+               ROCR_VISIBLE_DEVICES="-1")
+    r = subprocess.run([sys.executable, "-c", _CACHE_READER, LIB, json.dumps(shapes)],
+                       capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stderr
+    got = json.loads(r.stdout.strip().splitlines()[-1])
+    assert got[0] == [0, 16, 28, 1, 0, 2]
+    assert got[1] == [0, 8, 4, 0, 0, 0]
+    assert got[2][0] == 0 and got[2][1] in (4, 8, 16, 32)   # the heuristic's, not 64 lanes
