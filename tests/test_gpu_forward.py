@@ -442,6 +442,27 @@ def test_autotune_over_several_inputs(ocd):
         ocd.ocd_autotune_inputs(pb, [], [], z, L)
 
 
+def test_autotune_persists_its_plan(ocd, tmp_path, monkeypatch):
+    """With OCD_TUNE_CACHE set, the tuner writes its choice to that file (one JSON
+    object a line, keyed by GPU architecture and shape), stagger included."""
+    import json
+    cache = tmp_path / "plans.json"
+    monkeypatch.setenv("OCD_TUNE_CACHE", str(cache))
+    B, U, W, S, Q, K = 64, 8, 96, 6, 4, 2
+    wl = synth.make_workload(B, U, W, S, Q, 12.0, seed=[11, 1])
+    pb = ocd.problem(B, U, W, S, Q, K, "mmse", "f32", f32(wl["N0"]))
+    H, y = dev(wl["H"]), dev(wl["y"])
+    z = torch.empty(W, S, U, dtype=torch.complex64, device="cuda")
+    L = torch.empty(W, S, U, Q, dtype=torch.float32, device="cuda")
+    plan = ocd.ocd_autotune(pb, H, y, z, L, repeats=2)
+    shape = "|fwd|B%d|U%d|W%d|S%d|K%d|Q%d|m0|s0|l" % (B, U, W, S, K, Q)
+    recs = [json.loads(l) for l in cache.read_text().splitlines() if shape in l]
+    say("  persisted %s" % recs)
+    assert len(recs) == 2   # with and without per-sweep regularisers
+    for r in recs:
+        assert {k: r[k] for k in plan.as_dict()} == plan.as_dict()
+
+
 def test_autotune_returns_a_valid_plan(ocd):
     B, U, W, S, Q, K = 32, 8, 64, 1, 4, 3
     wl = synth.make_workload(B, U, W, S, Q, 10.0, seed=[11, 0])
