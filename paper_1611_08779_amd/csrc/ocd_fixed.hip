@@ -314,6 +314,8 @@ static hipError_t launch_fx_t(const FxParams &p, hipStream_t s)
 // lanes; B = 64 is faster at 16 lanes, 51 against 63 us).  At B = 128 the columns'
 // global-memory round trips made 32 lanes the faster (88 against 84 us); with the
 // columns staged in LDS, 16 lanes are (77.5 against 80.1 us, int16 pairs staged).
+// At B = 256 32 lanes stay ahead when staged (U = 8, 600 x 14 vectors: 81 against
+// 105 us; U = 32, 330 x 14: 229 against 244 us).
 static hipError_t launch_fx(const FxParams &p, hipStream_t s)
 {
     if (p.B <= 32) return launch_fx_t<16, 2>(p, s);
